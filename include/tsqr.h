@@ -1,0 +1,141 @@
+/*
+ * tsqr.h -- C ABI of the MI355X (gfx950) direct-TSQR library.
+ *
+ * Method: direct TSQR of Benson, Gleich & Demmel, "Direct QR factorizations for tall-and-skinny
+ * matrices in MapReduce architectures", Sec. III-B (three steps: Householder QR of every row
+ * block, QR of the stacked R factors, reconstruction Q_i = Q1_i Q2_i; SVD variant: SVD of R and
+ * U = Q U_R) with the recursive extension of Sec. III-C (Alg. 2: when the stacked R is too large
+ * for one task it is itself factored by direct TSQR).
+ *
+ * Conventions for every entry point
+ *   - Matrices are ROW-MAJOR: element (i,j) of X is X[i*ldx + j], ldx >= number of columns.
+ *     A row of A is one record of the paper's key-value layout (Sec. I-A).
+ *   - Every matrix/vector pointer is a DEVICE pointer; the caller owns all buffers.  The library
+ *     never allocates, frees or synchronises on the call path; all work is enqueued on `stream`
+ *     (a hipStream_t; NULL = default stream).  Calls are safe to capture in a HIP graph.
+ *   - `ws` is a device workspace of at least tsqr_workspace_bytes(...) bytes; its contents on
+ *     entry are ignored.
+ *   - Argument errors are returned synchronously, before anything is enqueued.
+ *   - Numerical conditions are reported through `d_info` (one device int32, written by the last
+ *     kernel of the call; read it after synchronising the stream):
+ *         0  success;
+ *         j  (j > 0) R[j-1][j-1] == 0: A is rank deficient (the paper assumes full rank, Sec. I);
+ *        -1  a non-finite value reached R (non-finite input).
+ *   - The factorization is the unique thin QR with diag(R) > 0 (A full rank).  Q is m x n with
+ *     orthonormal columns, R is n x n upper triangular (strict lower triangle written as 0).
+ *   - Supported: 1 <= n <= TSQR_NMAX, m >= n.  Values must be well inside the floating-point
+ *     range (|a_ij| < 1e150 in FP64, < 1e18 in FP32): column norms are formed without scaling.
+ */
+#ifndef TSQR_H
+#define TSQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TSQR_ABI_VERSION 1
+#define TSQR_NMAX 128
+
+typedef enum {
+    TSQR_OK = 0,
+    TSQR_ERR_INVALID_ARG = 1, /* NULL pointer, ld < n, m <= 0, n <= 0, bad enum */
+    TSQR_ERR_SHAPE = 2,       /* m < n or n > TSQR_NMAX */
+    TSQR_ERR_WORKSPACE = 3,   /* ws == NULL or ws_bytes too small */
+    TSQR_ERR_UNSUPPORTED = 4, /* option combination not implemented */
+    TSQR_ERR_HIP = 5          /* a HIP launch/runtime error */
+} tsqr_status;
+
+/* Arithmetic of the per-panel work (steps 1 and 3).  The stacked-R tree and the SVD of R are
+ * always FP64. */
+typedef enum {
+    TSQR_FP64 = 0,         /* everything FP64 */
+    TSQR_FP32_REFINED = 1, /* FP64 in/out: FP32 panels + FP32 Q1*Q2 GEMM, FP64 tree, then one FP64
+                              refinement pass that returns FP64 Q and R */
+    TSQR_FP32 = 2          /* FP32 panels and GEMM, FP64 tree, no refinement */
+} tsqr_precision;
+
+typedef struct {
+    int32_t struct_size; /* sizeof(tsqr_opts) */
+    int32_t precision;   /* tsqr_precision */
+    int32_t panel_rows;  /* 0 = library default for (n, precision); otherwise a supported height */
+    int32_t flags;       /* reserved, must be 0 */
+} tsqr_opts;
+
+/* Operation codes for tsqr_workspace_bytes. */
+typedef enum {
+    TSQR_OP_R = 0,
+    TSQR_OP_QR = 1,
+    TSQR_OP_SVD = 2,
+    TSQR_OP_QR_BACKWARD = 3,
+    TSQR_OP_SVD_BACKWARD = 4
+} tsqr_op;
+
+/* Default options: FP64, default panel height. */
+void tsqr_default_opts(tsqr_opts *opts);
+
+/* Workspace (bytes) needed by `op` on an m x n input with the given options (opts may be NULL). */
+tsqr_status tsqr_workspace_bytes(int32_t op, int64_t m, int64_t n, const tsqr_opts *opts,
+                                 size_t *bytes);
+
+/*
+ * R factor only (steps 1-2 of Sec. III-B; the indirect TSQR of Sec. II-B computes the same R,
+ * "any reduction tree computes R correctly").  A: m x n (lda); R: n x n (ldr), diag(R) > 0.
+ */
+tsqr_status tsqr_r(int64_t m, int64_t n, const double *A, int64_t lda, double *R, int64_t ldr,
+                   void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
+                   void *stream);
+
+/*
+ * Thin QR by direct TSQR (Sec. III-B steps 1-3): A (m x n, lda) = Q (m x n, ldq) R (n x n, ldr).
+ * With opts->precision == TSQR_FP32_REFINED the panels and the Q1*Q2 GEMM run in FP32 and one
+ * FP64 refinement pass (Y = A Rhat^{-1}, Y^T Y = Rc^T Rc, Q = Y Rc^{-1}, R = Rc Rhat) returns
+ * FP64 results; TSQR_FP32 returns the unrefined FP32-path result in FP64 storage.
+ */
+tsqr_status tsqr_qr(int64_t m, int64_t n, const double *A, int64_t lda, double *Q, int64_t ldq,
+                    double *R, int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                    const tsqr_opts *opts, void *stream);
+
+/*
+ * Thin SVD by direct TSQR (Sec. III-B): A = Q R, R = U_R diag(S) V^T, U = Q U_R, with U computed
+ * in the same pass as Q (U_R is passed to step 3).  U: m x n (ldu); S: n values, descending;
+ * V: n x n (ldv).  Gauge: each (u_k, v_k) pair is signed so that the largest-magnitude entry of
+ * v_k (lowest index on ties) is positive.  Q (ldq) and R (ldr) are optional (NULL = not wanted).
+ */
+tsqr_status tsqr_svd(int64_t m, int64_t n, const double *A, int64_t lda, double *U, int64_t ldu,
+                     double *S, double *V, int64_t ldv, double *Q, int64_t ldq, double *R,
+                     int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                     const tsqr_opts *opts, void *stream);
+
+/* FP32 input/output twins: FP32 panels and GEMM, FP64 tree and SVD (opts->precision ignored). */
+tsqr_status tsqr_r_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *R, int64_t ldr,
+                       void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
+                       void *stream);
+tsqr_status tsqr_qr_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *Q, int64_t ldq,
+                        float *R, int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                        const tsqr_opts *opts, void *stream);
+
+/*
+ * Kernel timing for benchmarks.  While enabled, every kernel launch the library makes is
+ * bracketed by a pair of HIP events recorded on the launch stream (events are created on first
+ * use and reused).  Not for use under graph capture.  tsqr_profile_collect waits for the recorded
+ * events, writes the summed milliseconds and launch counts of each kernel class c < nclasses
+ * into ms[c] / launches[c] (host arrays), and clears the record.
+ */
+tsqr_status tsqr_profile_enable(int32_t on);
+tsqr_status tsqr_profile_collect(double *ms, int64_t *launches, int32_t nclasses);
+int32_t tsqr_profile_num_classes(void);
+const char *tsqr_profile_class_name(int32_t c);
+
+/* Human-readable status name (static string). */
+const char *tsqr_status_string(tsqr_status status);
+/* TSQR_ABI_VERSION of the loaded library. */
+int32_t tsqr_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TSQR_H */

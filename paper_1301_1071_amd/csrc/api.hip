@@ -1,0 +1,427 @@
+// C ABI of libtsqr.so: argument checks, the level plan of the recursive tree, workspace layout
+// and the launch sequence.  See include/tsqr.h for the contract of every entry point.
+//
+// Launch sequence of tsqr_qr / tsqr_svd (all on the caller's stream, no host synchronisation):
+//   level 0 .. T   factor:  panels of the level matrix -> explicit Q1 panels + stacked R
+//                  (level 0 factors A; level L factors the stacked R of level L-1, Sec. III-C);
+//   finalize       R = D R~ (+ SVD of R), W_top = [D | D U_R], info;
+//   level T .. 0   apply:   Q1_p * W_p, W_p = rows [p n, p n + n) of the level above (the
+//                  reduce task's k-th key <-> rows (k-1)n+1..kn of its Q, Sec. III-B).
+#include <mutex>
+#include <string.h>
+#include <vector>
+
+#include "tsqr_internal.h"
+
+namespace tsqr {
+namespace {
+
+// ---- optional per-launch timing (benchmarks): HIP event pairs on the launch stream ----------
+enum ProfClass {
+    PC_FACTOR0 = 0, PC_FACTOR_TREE, PC_FINALIZE, PC_APPLY_TREE, PC_APPLY0, PC_REFINE,
+    PC_COUNT
+};
+const char *kProfNames[PC_COUNT] = {"factor_level0", "factor_tree", "finalize_svd",
+                                    "apply_tree", "apply_level0", "refine"};
+struct ProfRec { int cls; hipEvent_t a, b; };
+struct Profiler {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    std::vector<ProfRec> recs;
+    size_t next = 0;
+} g_prof;
+
+hipEvent_t prof_event()
+{
+    if (g_prof.next < g_prof.pool.size()) return g_prof.pool[g_prof.next++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_prof.pool.push_back(e);
+    g_prof.next = g_prof.pool.size();
+    return e;
+}
+
+struct ProfScope {
+    int cls;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(int c, hipStream_t s) : cls(c), st(s)
+    {
+        if (!g_prof.on) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        a = prof_event();
+        if (a) hipEventRecord(a, st);
+    }
+    ~ProfScope()
+    {
+        if (!a) return;
+        std::lock_guard<std::mutex> lk(g_prof.mu);
+        hipEvent_t b = prof_event();
+        if (!b) return;
+        hipEventRecord(b, st);
+        g_prof.recs.push_back({cls, a, b});
+    }
+};
+
+enum Op { OP_R = TSQR_OP_R, OP_QR = TSQR_OP_QR, OP_SVD = TSQR_OP_SVD };
+
+size_t elem_size(int dt) { return dt == F32 ? 4 : 8; }
+
+// panel height of a multi-panel level, and whether that level needs global scratch panels
+void multi_panel_height(int64_t n, int dtype, int requested, int *b, bool *global)
+{
+    const int bl = lds_panel_rows_max(n, dtype);
+    if (requested > 0) {
+        *b = requested;
+        *global = requested > bl;
+        return;
+    }
+    if (2 * bl >= 3 * n) {      // LDS panel at least 1.5 n tall: the tree shrinks fast enough
+        *b = lds_panel_rows(n, dtype);
+        *global = false;
+    } else {
+        *b = (int)(((4 * n) + 15) / 16 * 16);
+        *global = true;
+    }
+}
+
+tsqr_status validate_opts(const tsqr_opts *o, int64_t n)
+{
+    if (!o) return TSQR_OK;
+    if (o->struct_size != (int32_t)sizeof(tsqr_opts)) return TSQR_ERR_INVALID_ARG;
+    if (o->precision < TSQR_FP64 || o->precision > TSQR_FP32) return TSQR_ERR_INVALID_ARG;
+    if (o->flags != 0) return TSQR_ERR_INVALID_ARG;
+    if (o->panel_rows < 0) return TSQR_ERR_INVALID_ARG;
+    if (o->panel_rows > 0 && (o->panel_rows < n || o->panel_rows > (1 << 16)))
+        return TSQR_ERR_INVALID_ARG;
+    return TSQR_OK;
+}
+
+// Build the level plan and workspace layout.  want_q / want_u select the columns carried down.
+tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_opts *o,
+                       bool want_q, bool want_u, Plan &pl)
+{
+    if (m <= 0 || n <= 0) return TSQR_ERR_INVALID_ARG;
+    if (n > TSQR_NMAX || m < n) return TSQR_ERR_SHAPE;
+    tsqr_status vs = validate_opts(o, n);
+    if (vs != TSQR_OK) return vs;
+    pl = Plan();
+    pl.op = op;
+    pl.m = m;
+    pl.n = n;
+    pl.in_dtype = in_dtype;
+    pl.precision = o ? o->precision : TSQR_FP64;
+    if (in_dtype == F32) pl.precision = TSQR_FP32;
+    if (pl.precision == TSQR_FP32_REFINED && n > 64) return TSQR_ERR_UNSUPPORTED;
+    const int dtype0 = (pl.precision == TSQR_FP64) ? F64 : F32;
+    const bool refined = (pl.precision == TSQR_FP32_REFINED) && in_dtype == F64 && op == OP_QR;
+    const bool need_q = (op != OP_R) && !refined;
+    pl.k = need_q ? (int)((want_q ? n : 0) + (want_u ? n : 0)) : 0;
+
+    size_t off = kAlign;   // offset 0 is reserved so that 0 means "not allocated"
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return at;
+    };
+    int64_t rows = m;
+    for (int L = 0;; ++L) {
+        if (L >= kMaxLevels) return TSQR_ERR_UNSUPPORTED;
+        Level &lv = pl.lev[L];
+        lv.rows = rows;
+        lv.dtype = (L == 0) ? dtype0 : F64;
+        const int bl = lds_panel_rows_max(n, lv.dtype);
+        const int req = (L == 0 && o) ? o->panel_rows : 0;
+        if (rows <= bl && req == 0) {
+            lv.b = (int)rows;               // one panel, in LDS
+            lv.global = false;
+        } else if (rows <= 16 * n && req == 0) {
+            lv.b = (int)rows;               // one panel, too tall for LDS
+            lv.global = true;
+        } else {
+            multi_panel_height(n, lv.dtype, req, &lv.b, &lv.global);
+            if (lv.b > rows) { lv.b = (int)rows; }
+        }
+        lv.panels = ceil_div(rows, lv.b);
+        const size_t es = elem_size(lv.dtype);
+        if (need_q) lv.q1 = take(es * (size_t)rows * n);
+        lv.s = take(sizeof(double) * (size_t)lv.panels * n * n);
+        if (need_q && L >= 1) lv.x = take(sizeof(double) * (size_t)rows * pl.k);
+        if (lv.global) lv.gpanel = take(es * (size_t)lv.panels * n * (lv.b + 1));
+        pl.nlev = L + 1;
+        if (lv.panels == 1) break;
+        rows = lv.panels * n;
+    }
+    if (need_q) pl.wtop = take(sizeof(double) * (size_t)n * pl.k);
+    if (op == OP_SVD) {
+        pl.svd_g = take(sizeof(double) * (size_t)n * n);
+        pl.svd_v = take(sizeof(double) * (size_t)n * n);
+    }
+    if (refined) {
+        pl.refine_blocks = refine_blocks(m, n);
+        pl.refine = take(refine_scratch_bytes(m, n));
+        pl.svd_g = take(sizeof(double) * (size_t)n * n);   // Rhat
+    }
+    pl.total = off;
+    return TSQR_OK;
+}
+
+inline char *wsp(void *ws, size_t off) { return off ? (char *)ws + off : nullptr; }
+
+#define TSQR_HIP_CHECK(expr)                     \
+    do {                                         \
+        hipError_t e_ = (expr);                  \
+        if (e_ != hipSuccess) return TSQR_ERR_HIP; \
+    } while (0)
+
+// Steps 1-2 (+ finalize): every level's factor launch, then the top.
+tsqr_status run_factor_levels(const Plan &pl, const void *A, int64_t lda, void *ws,
+                              hipStream_t st)
+{
+    for (int L = 0; L < pl.nlev; ++L) {
+        const Level &lv = pl.lev[L];
+        const void *X = (L == 0) ? A : (const void *)wsp(ws, pl.lev[L - 1].s);
+        const int64_t ldx = (L == 0) ? lda : pl.n;
+        const int in_dt = (L == 0) ? pl.in_dtype : F64;
+        ProfScope ps(L == 0 ? PC_FACTOR0 : PC_FACTOR_TREE, st);
+        TSQR_HIP_CHECK(launch_factor(in_dt, lv.dtype, lv.rows, pl.n, lv.b, X, ldx,
+                                     wsp(ws, lv.q1), (double *)wsp(ws, lv.s),
+                                     lv.global ? wsp(ws, lv.gpanel) : nullptr, st));
+    }
+    return TSQR_OK;
+}
+
+// Step 3 down the tree.  Level 0 writes columns [0, k0) to out0 and [k0, k) to out1.
+tsqr_status run_apply_levels(const Plan &pl, void *ws, int out_dtype, void *out0, int64_t ld0,
+                             int k0, void *out1, int64_t ld1, hipStream_t st)
+{
+    const double *W = (const double *)wsp(ws, pl.wtop);
+    int64_t ldw = pl.k, wstride = 0;
+    for (int L = pl.nlev - 1; L >= 0; --L) {
+        const Level &lv = pl.lev[L];
+        ProfScope ps(L == 0 ? PC_APPLY0 : PC_APPLY_TREE, st);
+        if (L > 0) {
+            double *X = (double *)wsp(ws, lv.x);
+            TSQR_HIP_CHECK(launch_apply(F64, F64, lv.rows, pl.n, lv.b, wsp(ws, lv.q1), W, ldw,
+                                        wstride, pl.k, X, pl.k, pl.k, nullptr, 0, st));
+            W = X;
+            ldw = pl.k;
+            wstride = pl.n;
+        } else {
+            TSQR_HIP_CHECK(launch_apply(lv.dtype, out_dtype, lv.rows, pl.n, lv.b, wsp(ws, lv.q1),
+                                        W, ldw, wstride, pl.k, out0, ld0, k0, out1, ld1, st));
+        }
+    }
+    return TSQR_OK;
+}
+
+const tsqr_opts *opts_or_default(const tsqr_opts *o, tsqr_opts &tmp)
+{
+    if (o) return o;
+    tsqr_default_opts(&tmp);
+    return &tmp;
+}
+
+tsqr_status check_ws(const Plan &pl, void *ws, size_t ws_bytes)
+{
+    if (!ws || ws_bytes < pl.total) return TSQR_ERR_WORKSPACE;
+    return TSQR_OK;
+}
+
+tsqr_status do_r(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda, double *R,
+                 float *Rf, int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                 const tsqr_opts *opts, void *stream)
+{
+    if (!A || (!R && !Rf) || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldr < n) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    Plan pl;
+    tsqr_status s = build_plan(OP_R, m, n, in_dtype, opts_or_default(opts, tmp), false, false, pl);
+    if (s != TSQR_OK) return s;
+    if ((s = check_ws(pl, ws, ws_bytes)) != TSQR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
+    const Level &top = pl.lev[pl.nlev - 1];
+    ProfScope ps(PC_FINALIZE, st);
+    TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), R, Rf, ldr, nullptr, 0, 0,
+                                   0, nullptr, nullptr, 0, nullptr, nullptr, d_info, st));
+    return TSQR_OK;
+}
+
+tsqr_status do_qr(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda, void *Q,
+                  int64_t ldq, double *R, float *Rf, int64_t ldr, void *ws, size_t ws_bytes,
+                  int32_t *d_info, const tsqr_opts *opts, void *stream)
+{
+    if (!A || !Q || (!R && !Rf) || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldq < n || ldr < n) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    const tsqr_opts *o = opts_or_default(opts, tmp);
+    Plan pl;
+    tsqr_status s = build_plan(OP_QR, m, n, in_dtype, o, true, false, pl);
+    if (s != TSQR_OK) return s;
+    if ((s = check_ws(pl, ws, ws_bytes)) != TSQR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
+    const Level &top = pl.lev[pl.nlev - 1];
+    if (pl.k == 0) {
+        // precision form with refinement: Rhat from the FP32 path, then the FP64 pass
+        double *Rhat = (double *)wsp(ws, pl.svd_g);
+        {
+            ProfScope ps(PC_FINALIZE, st);
+            TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), Rhat, nullptr, n,
+                                           nullptr, 0, 0, 0, nullptr, nullptr, 0, nullptr,
+                                           nullptr, d_info, st));
+        }
+        ProfScope ps(PC_REFINE, st);
+        TSQR_HIP_CHECK(launch_refine(m, n, (const double *)A, lda, Rhat, (double *)Q, ldq, R, ldr,
+                                     wsp(ws, pl.refine), d_info, st));
+        return TSQR_OK;
+    }
+    {
+        ProfScope ps(PC_FINALIZE, st);
+        TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), R, Rf, ldr,
+                                       (double *)wsp(ws, pl.wtop), pl.k, 1, 0, nullptr, nullptr,
+                                       0, nullptr, nullptr, d_info, st));
+    }
+    return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, nullptr, 0, st);
+}
+
+}  // namespace
+}  // namespace tsqr
+
+using namespace tsqr;
+
+extern "C" {
+
+void tsqr_default_opts(tsqr_opts *opts)
+{
+    if (!opts) return;
+    memset(opts, 0, sizeof(*opts));
+    opts->struct_size = (int32_t)sizeof(tsqr_opts);
+    opts->precision = TSQR_FP64;
+}
+
+tsqr_status tsqr_workspace_bytes(int32_t op, int64_t m, int64_t n, const tsqr_opts *opts,
+                                 size_t *bytes)
+{
+    if (!bytes) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    const tsqr_opts *o = opts_or_default(opts, tmp);
+    Plan pl;
+    tsqr_status s;
+    switch (op) {
+    case TSQR_OP_R: s = build_plan(OP_R, m, n, F64, o, false, false, pl); break;
+    case TSQR_OP_QR: s = build_plan(OP_QR, m, n, F64, o, true, false, pl); break;
+    case TSQR_OP_SVD: s = build_plan(OP_SVD, m, n, F64, o, true, true, pl); break;
+    default: return TSQR_ERR_INVALID_ARG;
+    }
+    if (s != TSQR_OK) return s;
+    *bytes = pl.total;
+    return TSQR_OK;
+}
+
+tsqr_status tsqr_r(int64_t m, int64_t n, const double *A, int64_t lda, double *R, int64_t ldr,
+                   void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts, void *stream)
+{
+    return do_r(F64, m, n, A, lda, R, nullptr, ldr, ws, ws_bytes, d_info, opts, stream);
+}
+
+tsqr_status tsqr_r_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *R, int64_t ldr,
+                       void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
+                       void *stream)
+{
+    return do_r(F32, m, n, A, lda, nullptr, R, ldr, ws, ws_bytes, d_info, opts, stream);
+}
+
+tsqr_status tsqr_qr(int64_t m, int64_t n, const double *A, int64_t lda, double *Q, int64_t ldq,
+                    double *R, int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                    const tsqr_opts *opts, void *stream)
+{
+    return do_qr(F64, m, n, A, lda, Q, ldq, R, nullptr, ldr, ws, ws_bytes, d_info, opts, stream);
+}
+
+tsqr_status tsqr_qr_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *Q, int64_t ldq,
+                        float *R, int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                        const tsqr_opts *opts, void *stream)
+{
+    return do_qr(F32, m, n, A, lda, Q, ldq, nullptr, R, ldr, ws, ws_bytes, d_info, opts, stream);
+}
+
+tsqr_status tsqr_svd(int64_t m, int64_t n, const double *A, int64_t lda, double *U, int64_t ldu,
+                     double *S, double *V, int64_t ldv, double *Q, int64_t ldq, double *R,
+                     int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                     const tsqr_opts *opts, void *stream)
+{
+    if (!A || !U || !S || !V || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldu < n || ldv < n || (Q && ldq < n) || (R && ldr < n))
+        return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    const tsqr_opts *o = opts_or_default(opts, tmp);
+    if (o && o->precision == TSQR_FP32_REFINED) return TSQR_ERR_UNSUPPORTED;
+    Plan pl;
+    const bool want_q = Q != nullptr;
+    tsqr_status s = build_plan(OP_SVD, m, n, F64, o, want_q, true, pl);
+    if (s != TSQR_OK) return s;
+    if ((s = check_ws(pl, ws, ws_bytes)) != TSQR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
+    const Level &top = pl.lev[pl.nlev - 1];
+    {
+        ProfScope ps(PC_FINALIZE, st);
+        TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), R, nullptr, ldr,
+                                       (double *)wsp(ws, pl.wtop), pl.k, want_q ? 1 : 0, 1, S, V,
+                                       ldv, (double *)wsp(ws, pl.svd_g),
+                                       (double *)wsp(ws, pl.svd_v), d_info, st));
+    }
+    if (want_q) return run_apply_levels(pl, ws, F64, Q, ldq, (int)n, U, ldu, st);
+    return run_apply_levels(pl, ws, F64, U, ldu, (int)n, nullptr, 0, st);
+}
+
+const char *tsqr_status_string(tsqr_status status)
+{
+    switch (status) {
+    case TSQR_OK: return "TSQR_OK";
+    case TSQR_ERR_INVALID_ARG: return "TSQR_ERR_INVALID_ARG";
+    case TSQR_ERR_SHAPE: return "TSQR_ERR_SHAPE";
+    case TSQR_ERR_WORKSPACE: return "TSQR_ERR_WORKSPACE";
+    case TSQR_ERR_UNSUPPORTED: return "TSQR_ERR_UNSUPPORTED";
+    case TSQR_ERR_HIP: return "TSQR_ERR_HIP";
+    }
+    return "TSQR_ERR_UNKNOWN";
+}
+
+int32_t tsqr_abi_version(void) { return TSQR_ABI_VERSION; }
+
+tsqr_status tsqr_profile_enable(int32_t on)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.on = on != 0;
+    return TSQR_OK;
+}
+
+int32_t tsqr_profile_num_classes(void) { return PC_COUNT; }
+
+const char *tsqr_profile_class_name(int32_t c)
+{
+    return (c >= 0 && c < PC_COUNT) ? kProfNames[c] : "";
+}
+
+tsqr_status tsqr_profile_collect(double *ms, int64_t *launches, int32_t nclasses)
+{
+    if (!ms || !launches || nclasses < 0) return TSQR_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    for (int c = 0; c < nclasses; ++c) { ms[c] = 0.0; launches[c] = 0; }
+    tsqr_status st = TSQR_OK;
+    for (const ProfRec &r : g_prof.recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) { st = TSQR_ERR_HIP; continue; }
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) { st = TSQR_ERR_HIP; continue; }
+        if (r.cls < nclasses) { ms[r.cls] += t; launches[r.cls] += 1; }
+    }
+    g_prof.recs.clear();
+    g_prof.next = 0;
+    return st;
+}
+
+}  // extern "C"

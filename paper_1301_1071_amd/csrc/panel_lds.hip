@@ -1,0 +1,289 @@
+// Panel kernels with the row panel resident in LDS (general n <= TSQR_NMAX, FP64 or FP32).
+//
+// Step 1 of direct TSQR (Sec. III-B): one work-group factors one row panel A_p = Q1_p R_p with
+// Householder reflections (Sec. III-A), writes R_p into the stacked-R buffer (block p = rows
+// [p n, p n + n), the ordering the step-2 reduce task relies on) and, when Q is wanted, forms
+// Q1_p = H_1 ... H_n [I; 0] explicitly so that step 3 is a plain product Q1_p * Q2_p.
+// Step 3 (and every level of the recursive tree of Sec. III-C): out_p = Q1_p * W_p.
+//
+// Householder convention: for column k, x = A[k:, k], alpha = x_0, s2 = ||x_{1:}||^2;
+// beta = -sign(alpha) sqrt(alpha^2 + s2) (sign(0) = +1), tau = (beta - alpha) / beta and
+// v = [1; x_{1:} / (alpha - beta)], so that (I - tau v v^T) x = beta e_1.  s2 == 0 means no
+// reflection (tau = 0).  The below-diagonal part of x is kept unscaled in the panel and the scale
+// 1 / (alpha - beta) is folded into the update coefficients.
+#include "tsqr_internal.h"
+
+namespace tsqr {
+namespace {
+
+constexpr int kLdsBudget = 150 * 1024;   // bytes of LDS used by one panel work-group
+constexpr int kNpad = 128;               // column capacity of the small LDS arrays
+
+template <typename T>
+__device__ __forceinline__ T shfl_xor(T v, int mask) { return __shfl_xor(v, mask, 64); }
+
+template <typename Tin, typename T>
+__global__ void __launch_bounds__(kThreads)
+k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__restrict__ X,
+             int64_t ldx, T *__restrict__ q1, double *__restrict__ S, T *gpanel)
+{
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    __shared__ T red[4 * kNpad];                   // per-wave partial dots
+    __shared__ T rowk[kNpad];                      // row k of the panel, published per step
+    __shared__ T s_tau[kNpad];
+    __shared__ T s_umk[kNpad];                     // alpha - beta
+    __shared__ T s_beta[kNpad];                    // R_kk
+    // the panel: n columns of ldp rows (column-major), in LDS or, for panels too tall for LDS,
+    // in a global scratch panel (one per work-group)
+    T *P = gpanel ? gpanel + (size_t)blockIdx.x * n * ldp : reinterpret_cast<T *>(smem_raw);
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int NC = 1 << nc_log2;                   // columns per pass
+    const int G = 64 >> nc_log2;                   // row sub-groups per wave
+    const int cl = lane & (NC - 1);
+    const int g = lane >> nc_log2;
+    const int npass = (n + NC - 1) / NC;
+
+    const int64_t p = blockIdx.x;
+    const int64_t prow0 = p * (int64_t)b;
+    const int bp = (int)min((int64_t)b, rows - prow0);   // rows of A in this panel
+    const int re = max(bp, n);                            // rows processed (zero padded)
+
+    for (int e = tid; e < re * n; e += kThreads) {
+        const int i = e / n, c = e - i * n;
+        P[(size_t)c * ldp + i] = (i < bp) ? (T)X[(prow0 + i) * ldx + c] : T(0);
+    }
+    __syncthreads();
+
+    const int rs = (re + 3) / 4;
+    const int r0 = w * rs, r1 = min(re, r0 + rs);
+
+    // ---------------- factorization ------------------------------------------------------
+    for (int k = 0; k < n; ++k) {
+        const T *xk = P + (size_t)k * ldp;
+        const int i0 = max(r0, k + 1);
+        for (int ps = 0; ps < npass; ++ps) {
+            const int c = cl + ps * NC;
+            T d = T(0);
+            if (c >= k && c < n) {
+                const T *pc = P + (size_t)c * ldp;
+                for (int i = i0 + g; i < r1; i += G) d = fma(xk[i], pc[i], d);
+            }
+            for (int off = NC; off < 64; off <<= 1) d += shfl_xor(d, off);
+            if (g == 0 && c < n) {
+                red[w * kNpad + c] = d;
+                if (w == 0) rowk[c] = P[(size_t)c * ldp + k];
+            }
+        }
+        __syncthreads();
+        const T alpha = rowk[k];
+        const T s2 = red[k] + red[kNpad + k] + red[2 * kNpad + k] + red[3 * kNpad + k];
+        T tau = T(0), umk = T(0), beta = alpha;
+        if (s2 != T(0)) {
+            const T nrm = sqrt(alpha * alpha + s2);
+            beta = (alpha >= T(0)) ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            umk = alpha - beta;
+        }
+        if (tid == 0) { s_tau[k] = tau; s_umk[k] = umk; s_beta[k] = beta; }
+        if (tau != T(0)) {
+            const T inv = T(1) / umk;
+            for (int ps = 0; ps < npass; ++ps) {
+                const int c = cl + ps * NC;
+                if (c > k && c < n) {
+                    const T pcs = red[c] + red[kNpad + c] + red[2 * kNpad + c] + red[3 * kNpad + c];
+                    const T wc = rowk[c] + inv * pcs;          // v^T A[k:, c]
+                    const T coef = tau * wc * inv;
+                    T *pc = P + (size_t)c * ldp;
+                    for (int i = i0 + g; i < r1; i += G) pc[i] = fma(-coef, xk[i], pc[i]);
+                    if (w == 0 && g == 0) pc[k] = rowk[c] - tau * wc;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    // R_p into the stacked buffer: upper triangle of the top n rows, diagonal = beta
+    for (int e = tid; e < n * n; e += kThreads) {
+        const int r = e / n, c = e - r * n;
+        const double v = (c > r) ? (double)P[(size_t)c * ldp + r] : ((c == r) ? (double)s_beta[r] : 0.0);
+        S[(p * n + r) * n + c] = v;
+    }
+    if (q1 == nullptr) return;
+
+    // ---------------- explicit Q1 = H_1 ... H_n [I; 0], in place (backward accumulation) ---
+    for (int k = n - 1; k >= 0; --k) {
+        const T tau = s_tau[k];
+        const T umk = s_umk[k];
+        const T inv = (umk != T(0)) ? T(1) / umk : T(0);
+        const T *xk = P + (size_t)k * ldp;
+        const int i0 = max(r0, k + 1);
+        for (int ps = 0; ps < npass; ++ps) {
+            const int c = cl + ps * NC;
+            T d = T(0);
+            if (c > k && c < n && tau != T(0)) {
+                const T *pc = P + (size_t)c * ldp;
+                for (int i = i0 + g; i < r1; i += G) d = fma(xk[i], pc[i], d);
+            }
+            for (int off = NC; off < 64; off <<= 1) d += shfl_xor(d, off);
+            if (g == 0 && c < n) red[w * kNpad + c] = d;
+        }
+        __syncthreads();
+        if (tau != T(0)) {
+            for (int ps = 0; ps < npass; ++ps) {
+                const int c = cl + ps * NC;
+                if (c > k && c < n) {
+                    // row k of column c is zero here (cleared when column c was formed)
+                    const T wc = inv * (red[c] + red[kNpad + c] + red[2 * kNpad + c] + red[3 * kNpad + c]);
+                    const T coef = tau * wc * inv;
+                    T *pc = P + (size_t)c * ldp;
+                    for (int i = i0 + g; i < r1; i += G) pc[i] = fma(-coef, xk[i], pc[i]);
+                    if (w == 0 && g == 0) pc[k] = -tau * wc;
+                }
+            }
+        }
+        __syncthreads();
+        T *pk = P + (size_t)k * ldp;
+        const T sk = -tau * inv;
+        for (int i = tid; i < re; i += kThreads) {
+            const T v = (i > k) ? sk * pk[i] : ((i == k) ? T(1) - tau : T(0));
+            pk[i] = v;
+        }
+        __syncthreads();
+    }
+    for (int e = tid; e < bp * n; e += kThreads) {
+        const int i = e / n, c = e - i * n;
+        q1[(prow0 + i) * n + c] = P[(size_t)c * ldp + i];
+    }
+}
+
+// out rows of panel p = Q1_p (b x n) * W_p (n x k); each lane owns one output column.
+template <typename Tq, typename To, int NPM>
+__global__ void __launch_bounds__(kThreads)
+k_apply_rows(int64_t rows, int n, int b, const Tq *__restrict__ q1, const double *__restrict__ W,
+             int64_t ldw, int64_t wstride, int k, To *__restrict__ out0, int64_t ld0, int k0,
+             To *__restrict__ out1, int64_t ld1)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t p = blockIdx.x;
+    const int j = blockIdx.y * 64 + lane;
+    const double *Wp = W + p * wstride * ldw;
+    Tq wr[NPM];
+#pragma unroll
+    for (int c = 0; c < NPM; ++c) wr[c] = (c < n && j < k) ? (Tq)Wp[(int64_t)c * ldw + j] : Tq(0);
+    const int64_t rb = p * (int64_t)b;
+    const int64_t re = min(rows, rb + b);
+    for (int64_t r = rb + w; r < re; r += 4) {
+        const Tq *qr = q1 + r * n;
+        Tq acc = Tq(0);
+#pragma unroll
+        for (int c = 0; c < NPM; ++c) {
+            if (c < n) acc = fma(qr[c], wr[c], acc);
+        }
+        if (j < k0) out0[r * ld0 + j] = (To)acc;
+        else if (j < k) out1[r * ld1 + (j - k0)] = (To)acc;
+    }
+}
+
+template <typename T>
+size_t lds_bytes(int n, int b) { return sizeof(T) * (size_t)n * (b + 1); }
+
+int nc_log2_for(int64_t n)
+{
+    int l = 0;
+    while ((1 << l) < n && l < 6) ++l;
+    return l;
+}
+
+template <typename Tin, typename T>
+hipError_t factor_impl(int64_t rows, int64_t n, int b, const void *X, int64_t ldx, void *q1,
+                       double *S, void *gpanel, hipStream_t st)
+{
+    const size_t lds = gpanel ? 0 : lds_bytes<T>((int)n, b);
+    auto kern = k_factor_lds<Tin, T>;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void *)kern,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kLdsBudget + 8192);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    const int64_t panels = ceil_div(rows, b);
+    hipLaunchKernelGGL(kern, dim3((unsigned)panels), dim3(kThreads), lds, st, rows, (int)n, b,
+                       b + 1, nc_log2_for(n), (const Tin *)X, ldx, (T *)q1, S, (T *)gpanel);
+    return hipGetLastError();
+}
+
+template <typename Tq, typename To>
+hipError_t apply_impl(int64_t rows, int64_t n, int b, const void *q1, const double *W,
+                      int64_t ldw, int64_t wstride, int k, void *out0, int64_t ld0, int k0,
+                      void *out1, int64_t ld1, hipStream_t st)
+{
+    const int64_t panels = ceil_div(rows, b);
+    dim3 grid((unsigned)panels, (unsigned)ceil_div(k, 64));
+#define TSQR_APPLY_CASE(NPM)                                                                 \
+    hipLaunchKernelGGL((k_apply_rows<Tq, To, NPM>), grid, dim3(kThreads), 0, st, rows, (int)n, \
+                       b, (const Tq *)q1, W, ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1,  \
+                       ld1)
+    if (n <= 16) TSQR_APPLY_CASE(16);
+    else if (n <= 32) TSQR_APPLY_CASE(32);
+    else if (n <= 64) TSQR_APPLY_CASE(64);
+    else TSQR_APPLY_CASE(128);
+#undef TSQR_APPLY_CASE
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int lds_panel_rows_max(int64_t n, int dtype)
+{
+    const size_t es = (dtype == F32) ? 4 : 8;
+    const int64_t elems = (int64_t)(kLdsBudget / es);
+    int64_t b = elems / n - 1;
+    b = b / 16 * 16;
+    if (b > 4096) b = 4096;
+    return (int)b;
+}
+
+int lds_panel_rows(int64_t n, int dtype)
+{
+    int64_t b = lds_panel_rows_max(n, dtype);
+    if (b > 2048) b = 2048;
+    return (int)b;
+}
+
+hipError_t launch_factor(int in_dtype, int dtype, int64_t rows, int64_t n, int b, const void *X,
+                         int64_t ldx, void *q1, double *S, void *gpanel, hipStream_t st)
+{
+    if (dtype == F64) {
+        if (in_dtype == F64)
+            return factor_impl<double, double>(rows, n, b, X, ldx, q1, S, gpanel, st);
+        return factor_impl<float, double>(rows, n, b, X, ldx, q1, S, gpanel, st);
+    }
+    if (in_dtype == F64) return factor_impl<double, float>(rows, n, b, X, ldx, q1, S, gpanel, st);
+    return factor_impl<float, float>(rows, n, b, X, ldx, q1, S, gpanel, st);
+}
+
+hipError_t launch_apply(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
+                        const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
+                        void *out0, int64_t ld0, int k0, void *out1, int64_t ld1, hipStream_t st)
+{
+    if (q_dtype == F64) {
+        if (out_dtype == F64)
+            return apply_impl<double, double>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0,
+                                              out1, ld1, st);
+        return apply_impl<double, float>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1,
+                                         ld1, st);
+    }
+    if (out_dtype == F64)
+        return apply_impl<float, double>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1,
+                                         ld1, st);
+    return apply_impl<float, float>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1,
+                                    st);
+}
+
+}  // namespace tsqr

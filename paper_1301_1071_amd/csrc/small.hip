@@ -1,0 +1,184 @@
+// Top of the tree (one work-group): sign normalisation of R~, the info flag, and the SVD of R.
+//
+// Sec. III-B: the single reduce task ends with R~; the factorization with a positive diagonal is
+// unique for full-rank A (Sec. I), so R = D R~ with D = diag(sign(R~_jj)), sign(0) = +1, and the
+// step-3 blocks become Q2_p D.  For the SVD variant the reduce task also computes R = U_R S V^T
+// ("computing its SVD is cheap" -- the method is not named): one-sided Jacobi (Hestenes), columns
+// rotated until pairwise orthogonal, in parallel round-robin order.  U_R is passed down the tree
+// so that U = Q U_R comes out of step 3 in the same pass as Q.
+#include "tsqr_internal.h"
+
+namespace tsqr {
+namespace {
+
+constexpr int kSmallLdsLimit = 150 * 1024;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// player at position `pos` of round `r` in the round-robin tournament of np players
+__device__ __forceinline__ int rr_player(int pos, int r, int np)
+{
+    return pos == 0 ? 0 : 1 + (pos - 1 + r) % (np - 1);
+}
+
+__global__ void __launch_bounds__(kThreads)
+k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *__restrict__ Rf,
+           int64_t ldr, double *__restrict__ Wtop, int k, int want_q, int want_u,
+           double *__restrict__ S, double *__restrict__ V, int64_t ldv, double *G, double *Vw,
+           int use_lds, int32_t *__restrict__ info)
+{
+    extern __shared__ __align__(16) double sm[];
+    __shared__ double d_s[kNmaxPad];
+    __shared__ double s_sv[kNmaxPad];
+    __shared__ double s_sg[kNmaxPad];
+    __shared__ int perm[kNmaxPad];
+    __shared__ int s_zero, s_nonfinite, s_rot;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = tid >> 6;
+
+    if (tid == 0) { s_zero = 0x7fffffff; s_nonfinite = 0; }
+    __syncthreads();
+    for (int i = tid; i < n; i += kThreads) {
+        const double rii = Rt[(int64_t)i * n + i];
+        d_s[i] = (rii >= 0.0) ? 1.0 : -1.0;
+        if (rii == 0.0) atomicMin(&s_zero, i);
+    }
+    for (int e = tid; e < n * n; e += kThreads) {
+        const int r = e / n, c = e - r * n;
+        if (c >= r && !isfinite(Rt[e])) s_nonfinite = 1;
+    }
+    __syncthreads();
+    for (int e = tid; e < n * n; e += kThreads) {
+        const int r = e / n, c = e - r * n;
+        const double v = (c >= r) ? d_s[r] * Rt[e] : 0.0;
+        if (R) R[(int64_t)r * ldr + c] = v;
+        if (Rf) Rf[(int64_t)r * ldr + c] = (float)v;
+        if (want_q) Wtop[(int64_t)r * k + c] = (r == c) ? d_s[r] : 0.0;
+    }
+    const int kq = want_q ? n : 0;
+
+    if (want_u || S != nullptr) {
+        double *gG = use_lds ? sm : G;                     // column-major n x n
+        double *gV = use_lds ? sm + (size_t)n * n : Vw;
+        for (int e = tid; e < n * n; e += kThreads) {
+            const int r = e / n, c = e - r * n;
+            gG[(int64_t)c * n + r] = (c >= r) ? d_s[r] * Rt[e] : 0.0;
+            gV[(int64_t)c * n + r] = (r == c) ? 1.0 : 0.0;
+        }
+        const int np = n + (n & 1);
+        const double tol = 1e-15 * (double)n;
+        for (int sweep = 0; sweep < 60; ++sweep) {
+            __syncthreads();
+            if (tid == 0) s_rot = 0;
+            __syncthreads();
+            for (int round = 0; round < np - 1; ++round) {
+                for (int t = w; t < np / 2; t += kThreads / 64) {
+                    const int a = rr_player(t, round, np), bq = rr_player(np - 1 - t, round, np);
+                    const int p = min(a, bq), q = max(a, bq);
+                    if (q >= n) continue;
+                    double *gp = gG + (int64_t)p * n, *gq = gG + (int64_t)q * n;
+                    const double xp0 = lane < n ? gp[lane] : 0.0;
+                    const double xq0 = lane < n ? gq[lane] : 0.0;
+                    const double xp1 = lane + 64 < n ? gp[lane + 64] : 0.0;
+                    const double xq1 = lane + 64 < n ? gq[lane + 64] : 0.0;
+                    const double al = wave_sum(xp0 * xp0 + xp1 * xp1);
+                    const double be = wave_sum(xq0 * xq0 + xq1 * xq1);
+                    const double ga = wave_sum(xp0 * xq0 + xp1 * xq1);
+                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
+                        const double zeta = (be - al) / (2.0 * ga);
+                        const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) /
+                                          (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                        const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                        const double sn = cs * tt;
+                        double *vp = gV + (int64_t)p * n, *vq = gV + (int64_t)q * n;
+                        if (lane < n) {
+                            gp[lane] = cs * xp0 - sn * xq0;
+                            gq[lane] = sn * xp0 + cs * xq0;
+                            const double yp = vp[lane], yq = vq[lane];
+                            vp[lane] = cs * yp - sn * yq;
+                            vq[lane] = sn * yp + cs * yq;
+                        }
+                        if (lane + 64 < n) {
+                            gp[lane + 64] = cs * xp1 - sn * xq1;
+                            gq[lane + 64] = sn * xp1 + cs * xq1;
+                            const double yp = vp[lane + 64], yq = vq[lane + 64];
+                            vp[lane + 64] = cs * yp - sn * yq;
+                            vq[lane + 64] = sn * yp + cs * yq;
+                        }
+                        if (lane == 0) atomicAdd(&s_rot, 1);
+                    }
+                }
+                __syncthreads();
+            }
+            if (s_rot == 0) break;
+        }
+        __syncthreads();
+        for (int c = tid; c < n; c += kThreads) {
+            double ss = 0.0;
+            for (int r = 0; r < n; ++r) ss += gG[(int64_t)c * n + r] * gG[(int64_t)c * n + r];
+            s_sv[c] = sqrt(ss);
+        }
+        __syncthreads();
+        for (int c = tid; c < n; c += kThreads) {
+            int rank = 0;
+            for (int j = 0; j < n; ++j)
+                rank += (s_sv[j] > s_sv[c]) || (s_sv[j] == s_sv[c] && j < c);
+            perm[rank] = c;
+        }
+        __syncthreads();
+        for (int o = tid; o < n; o += kThreads) {
+            const int c = perm[o];
+            int imax = 0;
+            double vmax = -1.0;
+            for (int i = 0; i < n; ++i) {
+                const double a = fabs(gV[(int64_t)c * n + i]);
+                if (a > vmax) { vmax = a; imax = i; }
+            }
+            s_sg[o] = (gV[(int64_t)c * n + imax] < 0.0) ? -1.0 : 1.0;
+            if (S) S[o] = s_sv[c];
+        }
+        __syncthreads();
+        for (int e = tid; e < n * n; e += kThreads) {
+            const int i = e / n, o = e - i * n;
+            const int c = perm[o];
+            if (V) V[(int64_t)i * ldv + o] = s_sg[o] * gV[(int64_t)c * n + i];
+            if (want_u) {
+                const double s = s_sv[c];
+                const double u = (s > 0.0) ? s_sg[o] * gG[(int64_t)c * n + i] / s : 0.0;
+                Wtop[(int64_t)i * k + kq + o] = d_s[i] * u;
+            }
+        }
+    }
+    if (tid == 0) *info = s_nonfinite ? -1 : (s_zero == 0x7fffffff ? 0 : s_zero + 1);
+}
+
+}  // namespace
+
+hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, int64_t ldr,
+                           double *Wtop, int k, int want_q, int want_u, double *S, double *V,
+                           int64_t ldv, double *G, double *Vw, int32_t *info, hipStream_t st)
+{
+    const bool svd = want_u || S != nullptr;
+    const size_t need = svd ? 2 * sizeof(double) * (size_t)n * n : 0;
+    const int use_lds = (svd && need <= (size_t)kSmallLdsLimit) ? 1 : 0;
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_finalize,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           kSmallLdsLimit + 4096);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), use_lds ? need : 0, st, (int)n, Rt, R,
+                       Rf, ldr, Wtop, k, want_q, want_u, S, V, ldv, G, Vw, use_lds, info);
+    return hipGetLastError();
+}
+
+}  // namespace tsqr

@@ -1,0 +1,88 @@
+// Internal declarations shared by the HIP translation units of libtsqr.so (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/tsqr.h"
+
+namespace tsqr {
+
+constexpr int kThreads = 256;          // work-group size of the panel kernels (4 waves of 64)
+constexpr int kMaxLevels = 48;         // recursion depth limit of the in-HBM tree
+constexpr size_t kAlign = 256;         // workspace sub-buffer alignment
+constexpr int kNmaxPad = 128;          // column capacity of per-column LDS arrays (>= TSQR_NMAX)
+
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Which element type a buffer holds.
+enum Dtype : int { F64 = 0, F32 = 1 };
+
+// One level of the recursive direct TSQR (Sec. III-C, Alg. 2).  Level 0 factors A; level L >= 1
+// factors the stacked R factors of level L-1 (P_{L-1} * n rows, FP64).
+struct Level {
+    int64_t rows = 0;     // rows of the matrix factored at this level
+    int64_t panels = 0;   // number of row panels (map tasks)
+    int b = 0;            // panel height
+    int dtype = F64;      // arithmetic of the panel work at this level
+    size_t q1 = 0;        // offset of explicit Q1 panels (rows x n, ld n), 0 if not kept
+    size_t s = 0;         // offset of the stacked R output (panels*n x n, FP64)
+    size_t x = 0;         // offset of this level's Q (rows x k, FP64), levels >= 1 only
+    size_t gpanel = 0;    // offset of global scratch panels (panels tall for LDS), 0 if unused
+    bool global = false;  // panel held in global scratch instead of LDS
+};
+
+struct Plan {
+    int op = 0;
+    int64_t m = 0, n = 0;
+    int precision = TSQR_FP64;
+    int in_dtype = F64;   // element type of A
+    int nlev = 0;
+    Level lev[kMaxLevels];
+    int k = 0;            // columns carried down the tree (n for Q or U, 2n for Q and U)
+    size_t wtop = 0;      // n x k FP64: [D | D U_R]
+    size_t svd_g = 0, svd_v = 0;   // n x n FP64 scratch for the Jacobi SVD
+    size_t refine = 0;    // refinement scratch (Gram partials etc.)
+    int refine_blocks = 0;
+    size_t total = 0;
+};
+
+// ---- launchers (panel_lds.hip) ------------------------------------------------------------
+// Default panel height for (n, dtype) of the LDS-resident panel kernel.
+int lds_panel_rows(int64_t n, int dtype);
+// Largest panel height the LDS-resident kernel supports for (n, dtype).
+int lds_panel_rows_max(int64_t n, int dtype);
+
+// Factor every panel of a rows x n matrix X (element type in_dtype, ld ldx) in `dtype`
+// arithmetic: write R_p (FP64) into S (panels*n x n) and, if q1 != nullptr, the explicit
+// Q1_p (rows x n, ld n, element type dtype).  gpanel != nullptr holds the panels in global
+// scratch (panels * n * (b + 1) elements) instead of LDS.
+hipError_t launch_factor(int in_dtype, int dtype, int64_t rows, int64_t n, int b,
+                         const void *X, int64_t ldx, void *q1, double *S, void *gpanel,
+                         hipStream_t st);
+
+// out = Q1 * W per panel: panel p (rows [p b, p b + b)) uses W rows [p*wstride, p*wstride + n).
+// Columns [0, k0) of the product go to out0 (ld0), columns [k0, k) to out1 (ld1).
+hipError_t launch_apply(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
+                        const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
+                        void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
+                        hipStream_t st);
+
+// ---- launchers (small.hip) -----------------------------------------------------------------
+// Top of the tree: R = D Rt (D = diag(sign(Rt_jj)), sign(0) = +1) written to R (FP64, ldr) or Rf
+// (FP32, ldr); W_top (n x k) = [D | D U_R] (Q columns first if want_q, then U columns if want_u);
+// the SVD of R (one-sided Jacobi) when want_u or S != nullptr.  Sets *info.
+hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, int64_t ldr,
+                           double *Wtop, int k, int want_q, int want_u, double *S, double *V,
+                           int64_t ldv, double *G, double *Vw, int32_t *info, hipStream_t st);
+
+// ---- launchers (refine.hip) ----------------------------------------------------------------
+int refine_blocks(int64_t m, int64_t n);
+size_t refine_scratch_bytes(int64_t m, int64_t n);
+hipError_t launch_refine(int64_t m, int64_t n, const double *A, int64_t lda, double *Rhat,
+                         double *Q, int64_t ldq, double *R, int64_t ldr, void *scratch,
+                         int32_t *info, hipStream_t st);
+
+}  // namespace tsqr

@@ -1,0 +1,129 @@
+"""Python entry points over libtsqr.so: argument marshalling only.
+
+Every step of the factorization runs in the library's HIP kernels; this module allocates the
+outputs and the workspace with torch on the input's device, passes raw pointers and the current
+HIP stream, and turns non-OK statuses into exceptions.  Inputs must be CUDA (HIP) tensors; there
+is no CPU path.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import check, lib, make_opts
+
+
+def _require_gpu_matrix(A: torch.Tensor, dtypes=(torch.float64,)) -> None:
+    if not isinstance(A, torch.Tensor) or A.dim() != 2:
+        raise TypeError("A must be a 2-D torch tensor")
+    if A.device.type != "cuda":
+        raise TypeError("A must live on the GPU (device 'cuda'); the library has no CPU path")
+    if A.dtype not in dtypes:
+        raise TypeError("unsupported dtype %s" % A.dtype)
+    if A.stride(1) != 1:
+        raise ValueError("A must be row-major with unit column stride")
+
+
+def _stream(dev: torch.device) -> ctypes.c_void_p:
+    return ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+
+
+def _p(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def workspace_bytes(op: str, m: int, n: int, precision: str = "fp64", panel_rows: int = 0) -> int:
+    o = make_opts(precision, panel_rows)
+    out = ctypes.c_size_t(0)
+    check(lib().tsqr_workspace_bytes(_lib.OPS[op], m, n, ctypes.byref(o), ctypes.byref(out)),
+          "tsqr_workspace_bytes")
+    return int(out.value)
+
+
+def _workspace(op, m, n, precision, panel_rows, device):
+    nbytes = workspace_bytes(op, m, n, precision, panel_rows)
+    return torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+
+def _info_check(info: torch.Tensor, check_info: bool, where: str) -> None:
+    if check_info:
+        v = int(info.item())
+        if v != 0:
+            raise torch.linalg.LinAlgError("%s: info = %d (%s)" % (
+                where, v, "non-finite input" if v == -1 else
+                ("refinement breakdown" if v == -2 else "R[%d][%d] == 0 (rank deficient)" % (v - 1, v - 1))))
+
+
+def r(A: torch.Tensor, panel_rows: int = 0, ws: torch.Tensor | None = None,
+      check_info: bool = True) -> torch.Tensor:
+    """R factor of A (steps 1-2 of direct TSQR), diag(R) > 0.  FP64 or FP32 input."""
+    _require_gpu_matrix(A, (torch.float64, torch.float32))
+    m, n = A.shape
+    f32 = A.dtype == torch.float32
+    R = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    o = make_opts("fp64", panel_rows)
+    if ws is None:
+        ws = _workspace("r", m, n, "fp32" if f32 else "fp64", panel_rows, A.device)
+    fn = lib().tsqr_r_f32 if f32 else lib().tsqr_r
+    check(fn(m, n, _p(A), A.stride(0), _p(R), n, _p(ws), ws.numel(), _p(info), ctypes.byref(o),
+             _stream(A.device)), fn.__name__)
+    _info_check(info, check_info, "tsqr_r")
+    return R
+
+
+def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
+       ws: torch.Tensor | None = None, out=None, check_info: bool = True):
+    """Thin QR by direct TSQR: returns (Q, R).  precision in {"fp64", "fp32", "fp32_refined"}
+    for FP64 input; FP32 input always runs the FP32 path."""
+    _require_gpu_matrix(A, (torch.float64, torch.float32))
+    m, n = A.shape
+    f32 = A.dtype == torch.float32
+    if out is None:
+        Q = torch.empty((m, n), dtype=A.dtype, device=A.device)
+        R = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    else:
+        Q, R = out
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    prec = "fp32" if f32 else precision
+    o = make_opts(prec, panel_rows)
+    if ws is None:
+        ws = _workspace("qr", m, n, prec, panel_rows, A.device)
+    fn = lib().tsqr_qr_f32 if f32 else lib().tsqr_qr
+    check(fn(m, n, _p(A), A.stride(0), _p(Q), Q.stride(0), _p(R), R.stride(0), _p(ws), ws.numel(),
+             _p(info), ctypes.byref(o), _stream(A.device)), fn.__name__)
+    _info_check(info, check_info, "tsqr_qr")
+    return Q, R
+
+
+def svd(A: torch.Tensor, want_qr: bool = False, panel_rows: int = 0,
+        ws: torch.Tensor | None = None, out=None, check_info: bool = True):
+    """Thin SVD by direct TSQR: returns (U, S, V) or (U, S, V, Q, R) with want_qr."""
+    _require_gpu_matrix(A)
+    m, n = A.shape
+    if out is None:
+        U = torch.empty((m, n), dtype=A.dtype, device=A.device)
+        S = torch.empty((n,), dtype=A.dtype, device=A.device)
+        V = torch.empty((n, n), dtype=A.dtype, device=A.device)
+        Q = torch.empty((m, n), dtype=A.dtype, device=A.device) if want_qr else None
+        R = torch.empty((n, n), dtype=A.dtype, device=A.device) if want_qr else None
+    else:
+        U, S, V, Q, R = out
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    o = make_opts("fp64", panel_rows)
+    if ws is None:
+        nb = _svd_ws_bytes(m, n, want_qr, panel_rows)
+        ws = torch.empty(nb, dtype=torch.uint8, device=A.device)
+    check(lib().tsqr_svd(m, n, _p(A), A.stride(0), _p(U), U.stride(0), _p(S), _p(V), V.stride(0),
+                         _p(Q), Q.stride(0) if Q is not None else 0, _p(R),
+                         R.stride(0) if R is not None else 0, _p(ws), ws.numel(), _p(info),
+                         ctypes.byref(o), _stream(A.device)), "tsqr_svd")
+    _info_check(info, check_info, "tsqr_svd")
+    return (U, S, V, Q, R) if want_qr else (U, S, V)
+
+
+def _svd_ws_bytes(m, n, want_qr, panel_rows):
+    # the workspace query reports the SVD plan with Q and U both carried (the larger case)
+    return workspace_bytes("svd", m, n, "fp64", panel_rows)

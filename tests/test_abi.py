@@ -1,0 +1,111 @@
+"""CPU checks of the C ABI: the library loads, exports every function include/tsqr.h declares, and
+rejects bad arguments synchronously, before anything reaches the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1301_1071_amd import _lib
+from paper_1301_1071_amd._lib import lib, make_opts
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "tsqr.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w\s\*]*?\b(tsqr_\w+)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_symbols_exported():
+    names = declared_functions()
+    assert "tsqr_qr" in names and "tsqr_svd" in names and "tsqr_r" in names
+    h = lib()
+    for nm in names:
+        assert hasattr(h, nm), nm
+    # and the binding's signature table covers exactly the declared functions
+    assert set(_lib.SIGNATURES) == set(names)
+
+
+def test_abi_version_and_strings():
+    assert lib().tsqr_abi_version() == 1
+    for code, name in _lib.STATUS_NAMES.items():
+        assert lib().tsqr_status_string(code).decode() == name
+
+
+def _ws(op, m, n, opts=None):
+    out = ctypes.c_size_t(0)
+    st = lib().tsqr_workspace_bytes(_lib.OPS[op], m, n, ctypes.byref(opts) if opts else None,
+                                    ctypes.byref(out))
+    return st, out.value
+
+
+def test_workspace_query():
+    st, b1 = _ws("qr", 100_000, 10)
+    assert st == 0 and b1 >= 100_000 * 10 * 8
+    st, b2 = _ws("qr", 200_000, 10)
+    assert st == 0 and b2 > b1
+    st, br = _ws("r", 100_000, 10)
+    assert st == 0 and br < b1          # R only keeps no Q1 panels
+    st, bs = _ws("svd", 100_000, 10)
+    assert st == 0 and bs > b1          # Q and U carried down the tree
+    assert _ws("qr", 5, 10)[0] == 2     # m < n
+    assert _ws("qr", 1000, 129)[0] == 2  # n > TSQR_NMAX
+    assert _ws("qr", 0, 10)[0] == 1
+    assert _ws("qr", 1000, 0)[0] == 1
+    assert lib().tsqr_workspace_bytes(9, 10, 1, None, ctypes.byref(ctypes.c_size_t())) == 1
+
+
+def test_opts_validation():
+    o = make_opts("fp64")
+    assert _ws("qr", 1000, 10, o)[0] == 0
+    o.struct_size = 4
+    assert _ws("qr", 1000, 10, o)[0] == 1
+    o = make_opts("fp64"); o.precision = 7
+    assert _ws("qr", 1000, 10, o)[0] == 1
+    o = make_opts("fp64"); o.flags = 1
+    assert _ws("qr", 1000, 10, o)[0] == 1
+    o = make_opts("fp64", panel_rows=5)          # shorter than n
+    assert _ws("qr", 1000, 10, o)[0] == 1
+    o = make_opts("fp64", panel_rows=512)
+    assert _ws("qr", 100_000, 10, o)[0] == 0
+    o = make_opts("fp32_refined")
+    assert _ws("qr", 100_000, 100, o)[0] == 4    # refinement implemented for n <= 64
+
+
+FAKE = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+
+
+def _gpu_visible():
+    import torch
+    return torch.cuda.is_available()
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="fake device pointers are only passed where no GPU exists")
+def test_entry_points_reject_bad_arguments_without_gpu():
+    L = lib()
+    info = FAKE
+    # NULL input
+    assert L.tsqr_qr(100, 10, None, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, None, None) == 1
+    # ld < n
+    assert L.tsqr_qr(100, 10, FAKE, 9, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, None, None) == 1
+    assert L.tsqr_r(100, 10, FAKE, 10, FAKE, 9, FAKE, 1 << 30, info, None, None) == 1
+    # shapes
+    assert L.tsqr_qr(5, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, None, None) == 2
+    assert L.tsqr_r(1000, 200, FAKE, 200, FAKE, 200, FAKE, 1 << 30, info, None, None) == 2
+    # workspace missing or too small
+    assert L.tsqr_qr(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, None, 1 << 30, info, None, None) == 3
+    assert L.tsqr_qr(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 16, info, None, None) == 3
+    # missing info
+    assert L.tsqr_r(100, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, None, None, None) == 1
+    # svd: missing outputs, bad ld
+    assert L.tsqr_svd(100, 10, FAKE, 10, None, 10, FAKE, FAKE, 10, None, 0, None, 0, FAKE,
+                      1 << 30, info, None, None) == 1
+    assert L.tsqr_svd(100, 10, FAKE, 10, FAKE, 10, FAKE, FAKE, 9, None, 0, None, 0, FAKE,
+                      1 << 30, info, None, None) == 1
+    # f32 twins
+    assert L.tsqr_qr_f32(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 16, info, None, None) == 3
+    assert L.tsqr_r_f32(5, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, None, None) == 2
