@@ -131,6 +131,9 @@ const char *tsqr_profile_class_name(int32_t c);
 
 /* Human-readable status name (static string). */
 const char *tsqr_status_string(tsqr_status status);
+/* Description of the calling thread's most recent TSQR_ERR_HIP (HIP error text and the failing
+ * library call); "" if none. */
+const char *tsqr_last_error(void);
 /* TSQR_ABI_VERSION of the loaded library. */
 int32_t tsqr_abi_version(void);
 

@@ -38,6 +38,7 @@ SIGNATURES = {
     "tsqr_profile_class_name": (ctypes.c_char_p, [_i32]),
     "tsqr_status_string": (ctypes.c_char_p, [_i32]),
     "tsqr_abi_version": (_i32, []),
+    "tsqr_last_error": (ctypes.c_char_p, []),
 }
 
 
@@ -80,6 +81,8 @@ class TSQRError(RuntimeError):
 
 def check(status: int, where: str) -> None:
     if status != TSQR_OK:
+        if status == 5:
+            where = "%s [%s]" % (where, lib().tsqr_last_error().decode())
         raise TSQRError(status, where)
 
 

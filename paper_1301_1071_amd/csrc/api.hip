@@ -8,6 +8,7 @@
 //   level T .. 0   apply:   Q1_p * W_p, W_p = rows [p n, p n + n) of the level above (the
 //                  reduce task's k-th key <-> rows (k-1)n+1..kn of its Q, Sec. III-B).
 #include <mutex>
+#include <stdio.h>
 #include <string.h>
 #include <vector>
 
@@ -63,6 +64,15 @@ struct ProfScope {
         g_prof.recs.push_back({cls, a, b});
     }
 };
+
+// text of the most recent HIP failure (per thread), for tsqr_last_error()
+thread_local char g_last_error[512] = "";
+
+void set_last_error(hipError_t e, const char *what, int line)
+{
+    snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in %.300s [api.hip:%d]",
+             hipGetErrorString(e), (int)e, what, line);
+}
 
 enum Op { OP_R = TSQR_OP_R, OP_QR = TSQR_OP_QR, OP_SVD = TSQR_OP_SVD };
 
@@ -169,10 +179,13 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
 
 inline char *wsp(void *ws, size_t off) { return off ? (char *)ws + off : nullptr; }
 
-#define TSQR_HIP_CHECK(expr)                     \
-    do {                                         \
-        hipError_t e_ = (expr);                  \
-        if (e_ != hipSuccess) return TSQR_ERR_HIP; \
+#define TSQR_HIP_CHECK(expr)                                                                \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            set_last_error(e_, #expr, __LINE__);                                            \
+            return TSQR_ERR_HIP;                                                            \
+        }                                                                                   \
     } while (0)
 
 // Steps 1-2 (+ finalize): every level's factor launch, then the top.
@@ -392,6 +405,8 @@ const char *tsqr_status_string(tsqr_status status)
 }
 
 int32_t tsqr_abi_version(void) { return TSQR_ABI_VERSION; }
+
+const char *tsqr_last_error(void) { return g_last_error; }
 
 tsqr_status tsqr_profile_enable(int32_t on)
 {

@@ -204,13 +204,12 @@ hipError_t factor_impl(int64_t rows, int64_t n, int b, const void *X, int64_t ld
 {
     const size_t lds = gpanel ? 0 : lds_bytes<T>((int)n, b);
     auto kern = k_factor_lds<Tin, T>;
-    static bool attr_done = false;
-    if (!attr_done) {
+    static size_t attr_bytes = 0;     // largest dynamic LDS size requested so far
+    if (lds > 64 * 1024 && lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kLdsBudget + 8192);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        attr_done = true;
+        attr_bytes = lds;
     }
     const int64_t panels = ceil_div(rows, b);
     hipLaunchKernelGGL(kern, dim3((unsigned)panels), dim3(kThreads), lds, st, rows, (int)n, b,

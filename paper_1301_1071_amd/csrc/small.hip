@@ -168,15 +168,15 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
     const bool svd = want_u || S != nullptr;
     const size_t need = svd ? 2 * sizeof(double) * (size_t)n * n : 0;
     const int use_lds = (svd && need <= (size_t)kSmallLdsLimit) ? 1 : 0;
-    static bool attr_done = false;
-    if (!attr_done) {
+    const size_t lds = use_lds ? need : 0;
+    static size_t attr_bytes = 0;
+    if (lds > 64 * 1024 && lds > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)k_finalize,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           kSmallLdsLimit + 4096);
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
-        attr_done = true;
+        attr_bytes = lds;
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), use_lds ? need : 0, st, (int)n, Rt, R,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), lds, st, (int)n, Rt, R,
                        Rf, ldr, Wtop, k, want_q, want_u, S, V, ldv, G, Vw, use_lds, info);
     return hipGetLastError();
 }
