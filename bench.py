@@ -42,6 +42,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
     ap.add_argument("--cpu-sample-rows", type=int, default=0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -99,6 +101,14 @@ def main():
         desc = "direct TSQR (Q, R)" + (" FP32 panels + FP64 refinement" if precision != "fp64" else "")
         out_q = Q
 
+    if args.copy_probe:
+        # a plain copy of known size (1 GiB read + 1 GiB written) to calibrate HBM counters
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
