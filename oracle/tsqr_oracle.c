@@ -494,9 +494,12 @@ int oracle_svd_backward(int64_t m, int64_t n, const double *U, int64_t ldu, cons
  * The 2-norm of an n x n symmetric matrix is its largest |eigenvalue|, found by cyclic Jacobi.
  * ------------------------------------------------------------------------------------------- */
 
-/* largest |eigenvalue| of a symmetric n x n matrix (destroyed), cyclic Jacobi in long double */
+/* largest |eigenvalue| of a symmetric n x n matrix (destroyed), cyclic Jacobi in long double;
+ * NaN if any entry is not finite */
 static double sym_norm2(int64_t n, long double *Mx)
 {
+    for (int64_t i = 0; i < n * n; ++i)
+        if (!isfinite(Mx[i])) return NAN;
     for (int sweep = 0; sweep < 100; ++sweep) {
         long double off = 0.0L, tot = 0.0L;
         for (int64_t i = 0; i < n; ++i)

@@ -78,24 +78,6 @@ enum Op { OP_R = TSQR_OP_R, OP_QR = TSQR_OP_QR, OP_SVD = TSQR_OP_SVD };
 
 size_t elem_size(int dt) { return dt == F32 ? 4 : 8; }
 
-// panel height of a multi-panel level, and whether that level needs global scratch panels
-void multi_panel_height(int64_t n, int dtype, int requested, int *b, bool *global)
-{
-    const int bl = lds_panel_rows_max(n, dtype);
-    if (requested > 0) {
-        *b = requested;
-        *global = requested > bl;
-        return;
-    }
-    if (2 * bl >= 3 * n) {      // LDS panel at least 1.5 n tall: the tree shrinks fast enough
-        *b = lds_panel_rows(n, dtype);
-        *global = false;
-    } else {
-        *b = (int)(((4 * n) + 15) / 16 * 16);
-        *global = true;
-    }
-}
-
 tsqr_status validate_opts(const tsqr_opts *o, int64_t n)
 {
     if (!o) return TSQR_OK;
@@ -141,17 +123,24 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         Level &lv = pl.lev[L];
         lv.rows = rows;
         lv.dtype = (L == 0) ? dtype0 : F64;
-        const int bl = lds_panel_rows_max(n, lv.dtype);
         const int req = (L == 0 && o) ? o->panel_rows : 0;
-        if (rows <= bl && req == 0) {
-            lv.b = (int)rows;               // one panel, in LDS
+        const int bl = lds_panel_rows_max(n, lv.dtype);
+        const int breg = reg_panel_rows(n, lv.dtype);
+        if (req == 0 && (rows <= breg || (ceil_div(rows, breg) * n < rows && rows > 8 * n))) {
+            // default: register-resident panels of the register kernel's height
+            lv.reg = true;
             lv.global = false;
-        } else if (rows <= 16 * n && req == 0) {
-            lv.b = (int)rows;               // one panel, too tall for LDS
-            lv.global = true;
+            lv.b = (int)(rows < breg ? rows : breg);
+        } else if (req == 0) {
+            // a short stack that register panels would not shrink: one LDS (or global) panel
+            lv.reg = false;
+            lv.b = (int)rows;
+            lv.global = lv.b > bl;
         } else {
-            multi_panel_height(n, lv.dtype, req, &lv.b, &lv.global);
-            if (lv.b > rows) { lv.b = (int)rows; }
+            // an explicit panel height runs the LDS-resident kernel (global scratch if too tall)
+            lv.reg = false;
+            lv.b = (int)(req < rows ? req : rows);
+            lv.global = lv.b > bl;
         }
         lv.panels = ceil_div(rows, lv.b);
         const size_t es = elem_size(lv.dtype);
@@ -198,9 +187,13 @@ tsqr_status run_factor_levels(const Plan &pl, const void *A, int64_t lda, void *
         const int64_t ldx = (L == 0) ? lda : pl.n;
         const int in_dt = (L == 0) ? pl.in_dtype : F64;
         ProfScope ps(L == 0 ? PC_FACTOR0 : PC_FACTOR_TREE, st);
-        TSQR_HIP_CHECK(launch_factor(in_dt, lv.dtype, lv.rows, pl.n, lv.b, X, ldx,
-                                     wsp(ws, lv.q1), (double *)wsp(ws, lv.s),
-                                     lv.global ? wsp(ws, lv.gpanel) : nullptr, st));
+        if (lv.reg)
+            TSQR_HIP_CHECK(launch_factor_reg(in_dt, lv.dtype, lv.rows, pl.n, X, ldx,
+                                             wsp(ws, lv.q1), (double *)wsp(ws, lv.s), st));
+        else
+            TSQR_HIP_CHECK(launch_factor(in_dt, lv.dtype, lv.rows, pl.n, lv.b, X, ldx,
+                                         wsp(ws, lv.q1), (double *)wsp(ws, lv.s),
+                                         lv.global ? wsp(ws, lv.gpanel) : nullptr, st));
     }
     return TSQR_OK;
 }
@@ -216,14 +209,15 @@ tsqr_status run_apply_levels(const Plan &pl, void *ws, int out_dtype, void *out0
         ProfScope ps(L == 0 ? PC_APPLY0 : PC_APPLY_TREE, st);
         if (L > 0) {
             double *X = (double *)wsp(ws, lv.x);
-            TSQR_HIP_CHECK(launch_apply(F64, F64, lv.rows, pl.n, lv.b, wsp(ws, lv.q1), W, ldw,
-                                        wstride, pl.k, X, pl.k, pl.k, nullptr, 0, st));
+            TSQR_HIP_CHECK(launch_apply_staged(F64, F64, lv.rows, pl.n, lv.b, wsp(ws, lv.q1), W,
+                                               ldw, wstride, pl.k, X, pl.k, pl.k, nullptr, 0, st));
             W = X;
             ldw = pl.k;
             wstride = pl.n;
         } else {
-            TSQR_HIP_CHECK(launch_apply(lv.dtype, out_dtype, lv.rows, pl.n, lv.b, wsp(ws, lv.q1),
-                                        W, ldw, wstride, pl.k, out0, ld0, k0, out1, ld1, st));
+            TSQR_HIP_CHECK(launch_apply_staged(lv.dtype, out_dtype, lv.rows, pl.n, lv.b,
+                                               wsp(ws, lv.q1), W, ldw, wstride, pl.k, out0, ld0,
+                                               k0, out1, ld1, st));
         }
     }
     return TSQR_OK;

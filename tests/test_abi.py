@@ -109,3 +109,15 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     # f32 twins
     assert L.tsqr_qr_f32(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 16, info, None, None) == 3
     assert L.tsqr_r_f32(5, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, None, None) == 2
+
+
+def test_plan_terminates_for_every_width():
+    """The recursive tree (Sec. III-C) must shrink to one panel for every supported n."""
+    for n in range(1, 129):
+        for m in (n, n + 1, 2 * n + 1, 7 * n + 3, 1000, 4097, 100_000, 1_000_003):
+            if m < n:
+                continue
+            for op in ("r", "qr", "svd"):
+                st, nbytes = _ws(op, m, n)
+                assert st == 0, (op, m, n, st)
+                assert nbytes > 0

@@ -308,3 +308,11 @@ def test_svd_backward_matches_fd():
     # the S-only adjoint is U diag(dS) V^T exactly
     gs = oracle.svd_backward(U, S, V, None, dS, None)
     assert rel(gs, U @ np.diag(dS) @ V.T) <= 1e-14
+
+
+def test_metrics_report_nan_for_nonfinite_input():
+    Q = np.linalg.qr(np.random.default_rng(22).standard_normal((100, 3)))[0]
+    Q[5, 1] = np.nan
+    assert np.isnan(oracle.metric_orth(Q))
+    A = np.random.default_rng(23).standard_normal((100, 3))
+    assert np.isnan(oracle.metric_backward(A, Q, np.eye(3)))
