@@ -129,14 +129,11 @@ def main():
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
                for k, v in prof.items() if v[1] > 0}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    bpanel = None
     roof = None
     dom_ms_launch = prof[dom][0] / prof[dom][1]
     if dom == "factor_level0":
         # b of the level-0 panels as the plan picks it (LDS-resident panel height)
-        from paper_1301_1071_amd import _lib as L  # noqa: F401
-        bpanel = int(os.environ.get("TSQR_BENCH_B0", "0")) or None
-        b = bpanel or _default_b0(n, precision)
+        b = _lib.plan_levels("svd" if name == "svd-c50" else "qr", m, n, precision)[0][1]
         flops = level0_flops(m, n, b, form_q=True)
         byts = 8.0 * m * n * 2                  # read A, write Q1
         intensity = flops / byts
@@ -204,13 +201,6 @@ def main():
         line["cpu_baseline"] = cpu_baseline(name, A_h, n, args.cpu_sample_rows)
 
     print(json.dumps(line), flush=True)
-
-
-def _default_b0(n, precision):
-    # mirrors the library's default: tallest LDS-resident panel (150 KiB, column-major + 1 pad)
-    es = 4 if precision != "fp64" else 8
-    b = (150 * 1024 // es) // n - 1
-    return min(2048, b // 16 * 16)
 
 
 def cpu_baseline(name, A_h, n, sample_rows):

@@ -118,6 +118,16 @@ tsqr_status tsqr_qr_f32(int64_t m, int64_t n, const float *A, int64_t lda, float
                         const tsqr_opts *opts, void *stream);
 
 /*
+ * The recursive tree the library runs for `op` on an m x n input (Sec. III-C): level 0 factors A,
+ * level L >= 1 the stacked R factors of level L-1.  Writes the number of levels to *nlevels and,
+ * for the first max_levels levels, the rows of the level matrix and its panel height (host
+ * arrays).  Same argument errors as tsqr_workspace_bytes.
+ */
+tsqr_status tsqr_plan_levels(int32_t op, int64_t m, int64_t n, const tsqr_opts *opts,
+                             int32_t max_levels, int32_t *nlevels, int64_t *rows,
+                             int32_t *panel_rows);
+
+/*
  * Kernel timing for benchmarks.  While enabled, every kernel launch the library makes is
  * bracketed by a pair of HIP events recorded on the launch stream (events are created on first
  * use and reused).  Not for use under graph capture.  tsqr_profile_collect waits for the recorded

@@ -32,6 +32,8 @@ SIGNATURES = {
                            _vp]),
     "tsqr_svd": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
                         _vp, _sz, _vp, _vp, _vp]),
+    "tsqr_plan_levels": (_i32, [_i32, _i64, _i64, _vp, _i32, ctypes.POINTER(_i32),
+                                 ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "tsqr_profile_enable": (_i32, [_i32]),
     "tsqr_profile_collect": (_i32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), _i32]),
     "tsqr_profile_num_classes": (_i32, []),
@@ -97,3 +99,15 @@ def profile_collect() -> dict:
     cnt = (ctypes.c_int64 * n)()
     check(lib().tsqr_profile_collect(ms, cnt, n), "tsqr_profile_collect")
     return {lib().tsqr_profile_class_name(i).decode(): (ms[i], cnt[i]) for i in range(n)}
+
+
+def plan_levels(op: str, m: int, n: int, precision: str = "fp64", panel_rows: int = 0):
+    """[(rows, panel height)] of every level of the recursive tree the library runs."""
+    o = make_opts(precision, panel_rows)
+    cap = 64
+    nl = ctypes.c_int32(0)
+    rows = (ctypes.c_int64 * cap)()
+    prs = (ctypes.c_int32 * cap)()
+    check(lib().tsqr_plan_levels(OPS[op], m, n, ctypes.byref(o), cap, ctypes.byref(nl), rows, prs),
+          "tsqr_plan_levels")
+    return [(rows[i], prs[i]) for i in range(min(nl.value, cap))]

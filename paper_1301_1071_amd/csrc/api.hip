@@ -209,15 +209,15 @@ tsqr_status run_apply_levels(const Plan &pl, void *ws, int out_dtype, void *out0
         ProfScope ps(L == 0 ? PC_APPLY0 : PC_APPLY_TREE, st);
         if (L > 0) {
             double *X = (double *)wsp(ws, lv.x);
-            TSQR_HIP_CHECK(launch_apply_staged(F64, F64, lv.rows, pl.n, lv.b, wsp(ws, lv.q1), W,
-                                               ldw, wstride, pl.k, X, pl.k, pl.k, nullptr, 0, st));
+            TSQR_HIP_CHECK(launch_apply_mfma(F64, F64, lv.rows, pl.n, lv.b, wsp(ws, lv.q1), W,
+                                             ldw, wstride, pl.k, X, pl.k, pl.k, nullptr, 0, st));
             W = X;
             ldw = pl.k;
             wstride = pl.n;
         } else {
-            TSQR_HIP_CHECK(launch_apply_staged(lv.dtype, out_dtype, lv.rows, pl.n, lv.b,
-                                               wsp(ws, lv.q1), W, ldw, wstride, pl.k, out0, ld0,
-                                               k0, out1, ld1, st));
+            TSQR_HIP_CHECK(launch_apply_mfma(lv.dtype, out_dtype, lv.rows, pl.n, lv.b,
+                                             wsp(ws, lv.q1), W, ldw, wstride, pl.k, out0, ld0,
+                                             k0, out1, ld1, st));
         }
     }
     return TSQR_OK;
@@ -383,6 +383,31 @@ tsqr_status tsqr_svd(int64_t m, int64_t n, const double *A, int64_t lda, double 
     }
     if (want_q) return run_apply_levels(pl, ws, F64, Q, ldq, (int)n, U, ldu, st);
     return run_apply_levels(pl, ws, F64, U, ldu, (int)n, nullptr, 0, st);
+}
+
+tsqr_status tsqr_plan_levels(int32_t op, int64_t m, int64_t n, const tsqr_opts *opts,
+                             int32_t max_levels, int32_t *nlevels, int64_t *rows,
+                             int32_t *panel_rows)
+{
+    if (!nlevels || max_levels < 0 || (max_levels > 0 && (!rows || !panel_rows)))
+        return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    const tsqr_opts *o = opts_or_default(opts, tmp);
+    Plan pl;
+    tsqr_status s;
+    switch (op) {
+    case TSQR_OP_R: s = build_plan(OP_R, m, n, F64, o, false, false, pl); break;
+    case TSQR_OP_QR: s = build_plan(OP_QR, m, n, F64, o, true, false, pl); break;
+    case TSQR_OP_SVD: s = build_plan(OP_SVD, m, n, F64, o, true, true, pl); break;
+    default: return TSQR_ERR_INVALID_ARG;
+    }
+    if (s != TSQR_OK) return s;
+    *nlevels = pl.nlev;
+    for (int L = 0; L < pl.nlev && L < max_levels; ++L) {
+        rows[L] = pl.lev[L].rows;
+        panel_rows[L] = pl.lev[L].b;
+    }
+    return TSQR_OK;
 }
 
 const char *tsqr_status_string(tsqr_status status)

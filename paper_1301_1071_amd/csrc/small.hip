@@ -13,20 +13,23 @@ namespace {
 
 constexpr int kSmallLdsLimit = 150 * 1024;
 
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
-}
-
 // player at position `pos` of round `r` in the round-robin tournament of np players
 __device__ __forceinline__ int rr_player(int pos, int r, int np)
 {
     return pos == 0 ? 0 : 1 + (pos - 1 + r) % (np - 1);
 }
 
-__global__ void __launch_bounds__(kThreads)
+constexpr int kSvdThreads = 1024;   // 16 waves: 64 groups of 16 lanes, one column pair each
+
+// reduce over the 16 lanes of a group (xor offsets 8..1 stay inside the group)
+__device__ __forceinline__ double group16_sum(double v)
+{
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(kSvdThreads)
 k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *__restrict__ Rf,
            int64_t ldr, double *__restrict__ Wtop, int k, int want_q, int want_u,
            double *__restrict__ S, double *__restrict__ V, int64_t ldv, double *G, double *Vw,
@@ -40,22 +43,21 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
     __shared__ int s_zero, s_nonfinite, s_rot;
 
     const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int w = tid >> 6;
+    const int nth = blockDim.x;
 
     if (tid == 0) { s_zero = 0x7fffffff; s_nonfinite = 0; }
     __syncthreads();
-    for (int i = tid; i < n; i += kThreads) {
+    for (int i = tid; i < n; i += nth) {
         const double rii = Rt[(int64_t)i * n + i];
         d_s[i] = (rii >= 0.0) ? 1.0 : -1.0;
         if (rii == 0.0) atomicMin(&s_zero, i);
     }
-    for (int e = tid; e < n * n; e += kThreads) {
+    for (int e = tid; e < n * n; e += nth) {
         const int r = e / n, c = e - r * n;
         if (c >= r && !isfinite(Rt[e])) s_nonfinite = 1;
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += kThreads) {
+    for (int e = tid; e < n * n; e += nth) {
         const int r = e / n, c = e - r * n;
         const double v = (c >= r) ? d_s[r] * Rt[e] : 0.0;
         if (R) R[(int64_t)r * ldr + c] = v;
@@ -67,30 +69,40 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
     if (want_u || S != nullptr) {
         double *gG = use_lds ? sm : G;                     // column-major n x n
         double *gV = use_lds ? sm + (size_t)n * n : Vw;
-        for (int e = tid; e < n * n; e += kThreads) {
+        for (int e = tid; e < n * n; e += nth) {
             const int r = e / n, c = e - r * n;
             gG[(int64_t)c * n + r] = (c >= r) ? d_s[r] * Rt[e] : 0.0;
             gV[(int64_t)c * n + r] = (r == c) ? 1.0 : 0.0;
         }
-        const int np = n + (n & 1);
+        const int np = n + (n & 1);                    // players of the round-robin tournament
+        const int npairs = np / 2;
+        const int grp = tid >> 4, gl = tid & 15;       // 16-lane group and lane within it
+        const int ngrp = nth >> 4;
         const double tol = 1e-15 * (double)n;
         for (int sweep = 0; sweep < 60; ++sweep) {
             __syncthreads();
             if (tid == 0) s_rot = 0;
             __syncthreads();
             for (int round = 0; round < np - 1; ++round) {
-                for (int t = w; t < np / 2; t += kThreads / 64) {
+                for (int t = grp; t < npairs; t += ngrp) {      // uniform within each group
                     const int a = rr_player(t, round, np), bq = rr_player(np - 1 - t, round, np);
                     const int p = min(a, bq), q = max(a, bq);
                     if (q >= n) continue;
                     double *gp = gG + (int64_t)p * n, *gq = gG + (int64_t)q * n;
-                    const double xp0 = lane < n ? gp[lane] : 0.0;
-                    const double xq0 = lane < n ? gq[lane] : 0.0;
-                    const double xp1 = lane + 64 < n ? gp[lane + 64] : 0.0;
-                    const double xq1 = lane + 64 < n ? gq[lane + 64] : 0.0;
-                    const double al = wave_sum(xp0 * xp0 + xp1 * xp1);
-                    const double be = wave_sum(xq0 * xq0 + xq1 * xq1);
-                    const double ga = wave_sum(xp0 * xq0 + xp1 * xq1);
+                    double xp[kNmaxPad / 16], xq[kNmaxPad / 16];
+                    double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+                    for (int j = 0; j < kNmaxPad / 16; ++j) {
+                        const int i = gl + 16 * j;
+                        xp[j] = (i < n) ? gp[i] : 0.0;
+                        xq[j] = (i < n) ? gq[i] : 0.0;
+                        al = fma(xp[j], xp[j], al);
+                        be = fma(xq[j], xq[j], be);
+                        ga = fma(xp[j], xq[j], ga);
+                    }
+                    al = group16_sum(al);
+                    be = group16_sum(be);
+                    ga = group16_sum(ga);
                     if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
                         const double zeta = (be - al) / (2.0 * ga);
                         const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) /
@@ -98,21 +110,18 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
                         const double cs = 1.0 / sqrt(1.0 + tt * tt);
                         const double sn = cs * tt;
                         double *vp = gV + (int64_t)p * n, *vq = gV + (int64_t)q * n;
-                        if (lane < n) {
-                            gp[lane] = cs * xp0 - sn * xq0;
-                            gq[lane] = sn * xp0 + cs * xq0;
-                            const double yp = vp[lane], yq = vq[lane];
-                            vp[lane] = cs * yp - sn * yq;
-                            vq[lane] = sn * yp + cs * yq;
+#pragma unroll
+                        for (int j = 0; j < kNmaxPad / 16; ++j) {
+                            const int i = gl + 16 * j;
+                            if (i < n) {
+                                gp[i] = cs * xp[j] - sn * xq[j];
+                                gq[i] = sn * xp[j] + cs * xq[j];
+                                const double yp = vp[i], yq = vq[i];
+                                vp[i] = cs * yp - sn * yq;
+                                vq[i] = sn * yp + cs * yq;
+                            }
                         }
-                        if (lane + 64 < n) {
-                            gp[lane + 64] = cs * xp1 - sn * xq1;
-                            gq[lane + 64] = sn * xp1 + cs * xq1;
-                            const double yp = vp[lane + 64], yq = vq[lane + 64];
-                            vp[lane + 64] = cs * yp - sn * yq;
-                            vq[lane + 64] = sn * yp + cs * yq;
-                        }
-                        if (lane == 0) atomicAdd(&s_rot, 1);
+                        if (gl == 0) atomicAdd(&s_rot, 1);
                     }
                 }
                 __syncthreads();
@@ -120,20 +129,20 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
             if (s_rot == 0) break;
         }
         __syncthreads();
-        for (int c = tid; c < n; c += kThreads) {
+        for (int c = tid; c < n; c += nth) {
             double ss = 0.0;
             for (int r = 0; r < n; ++r) ss += gG[(int64_t)c * n + r] * gG[(int64_t)c * n + r];
             s_sv[c] = sqrt(ss);
         }
         __syncthreads();
-        for (int c = tid; c < n; c += kThreads) {
+        for (int c = tid; c < n; c += nth) {
             int rank = 0;
             for (int j = 0; j < n; ++j)
                 rank += (s_sv[j] > s_sv[c]) || (s_sv[j] == s_sv[c] && j < c);
             perm[rank] = c;
         }
         __syncthreads();
-        for (int o = tid; o < n; o += kThreads) {
+        for (int o = tid; o < n; o += nth) {
             const int c = perm[o];
             int imax = 0;
             double vmax = -1.0;
@@ -145,7 +154,7 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
             if (S) S[o] = s_sv[c];
         }
         __syncthreads();
-        for (int e = tid; e < n * n; e += kThreads) {
+        for (int e = tid; e < n * n; e += nth) {
             const int i = e / n, o = e - i * n;
             const int c = perm[o];
             if (V) V[(int64_t)i * ldv + o] = s_sg[o] * gV[(int64_t)c * n + i];
@@ -176,7 +185,7 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
         if (e != hipSuccess) return e;
         attr_bytes = lds;
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), lds, st, (int)n, Rt, R,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kSvdThreads), lds, st, (int)n, Rt, R,
                        Rf, ldr, Wtop, k, want_q, want_u, S, V, ldv, G, Vw, use_lds, info);
     return hipGetLastError();
 }

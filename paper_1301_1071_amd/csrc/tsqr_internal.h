@@ -72,7 +72,7 @@ hipError_t launch_apply(int q_dtype, int out_dtype, int64_t rows, int64_t n, int
                         hipStream_t st);
 
 // ---- launchers (panel_reg.hip): register-resident panels, the default for every level -------
-// Panel height of the register kernel for (n, dtype): 1024/512/256/192 rows (FP64, n <= 16/32/
+// Panel height of the register kernel for (n, dtype): 512/256/192/192 rows (FP64, n <= 16/32/
 // 64/128), twice that for FP32.
 int reg_panel_rows(int64_t n, int dtype);
 hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, const void *X,
@@ -82,6 +82,12 @@ hipError_t launch_apply_staged(int q_dtype, int out_dtype, int64_t rows, int64_t
                                const void *q1, const double *W, int64_t ldw, int64_t wstride,
                                int k, void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
                                hipStream_t st);
+
+// ---- launchers (apply_mfma.hip): step 3 on the matrix cores (same contract as launch_apply) --
+hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
+                             const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
+                             void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
+                             hipStream_t st);
 
 // ---- launchers (small.hip) -----------------------------------------------------------------
 // Top of the tree: R = D Rt (D = diag(sign(Rt_jj)), sign(0) = +1) written to R (FP64, ldr) or Rf

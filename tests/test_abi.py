@@ -121,3 +121,14 @@ def test_plan_terminates_for_every_width():
                 st, nbytes = _ws(op, m, n)
                 assert st == 0, (op, m, n, st)
                 assert nbytes > 0
+
+
+def test_plan_levels_shape():
+    from paper_1301_1071_amd._lib import plan_levels
+    lv = plan_levels("qr", 4_000_000, 50)
+    assert lv[0][0] == 4_000_000
+    for (rows, b), (rows_next, _) in zip(lv, lv[1:]):
+        panels = -(-rows // b)
+        assert rows_next == panels * 50          # the stacked R of the level below
+        assert rows_next < rows
+    assert lv[-1][1] == lv[-1][0]                # the top is one panel
