@@ -37,7 +37,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="svd-c50", choices=["svd-c50", "qr-small", "mixed-c25"])
+    ap.add_argument("--workload", default="svd-c50",
+                    choices=["svd-c50", "qr-small", "mixed-c25", "grad-c100"])
     ap.add_argument("--rows", type=int, default=0, help="override m (same recipe and seed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -89,6 +90,25 @@ def main():
         desc = "direct TSQR + SVD (Q, R, U, S, V), A = G diag(logspace(0,-12)) V^T"
         out_q = Q
         precision = "fp64"
+    elif name == "grad-c100":
+        # one differentiable pass: forward QR, then the QR adjoint for cotangents (dQ, dR)
+        precision = "fp64"
+        ct = workloads.cotangents(m, n)
+        dQ = torch.from_numpy(ct["dQ"]).to(dev)
+        dR = torch.from_numpy(ct["dR"]).to(dev)
+        Q = torch.empty((m, n), dtype=torch.float64, device=dev)
+        R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        dA = torch.empty((m, n), dtype=torch.float64, device=dev)
+        ws = torch.empty(max(tsqr.workspace_bytes("qr", m, n),
+                             tsqr.workspace_bytes("qr_backward", m, n)), dtype=torch.uint8,
+                         device=dev)
+
+        def step():
+            tsqr.qr(A, ws=ws, out=(Q, R), check_info=False)
+            tsqr.qr_backward(A, dQ, dR, ws=ws, out=dA, check_info=False)
+        alg_bytes = 2 * 8.0 * m * n + 3 * 8.0 * m * n   # fwd: A, Q; bwd: A, dQ, dA
+        desc = "direct TSQR forward (Q, R) + closed-form QR adjoint (dA), Q recomputed from A"
+        out_q = Q
     else:
         precision = "fp64" if name == "qr-small" else "fp32_refined"
         Q = torch.empty((m, n), dtype=torch.float64, device=dev)
@@ -129,38 +149,9 @@ def main():
     kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
                for k, v in prof.items() if v[1] > 0}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    roof = None
     dom_ms_launch = prof[dom][0] / prof[dom][1]
-    if dom == "factor_level0":
-        # b of the level-0 panels as the plan picks it (LDS-resident panel height)
-        b = _lib.plan_levels("svd" if name == "svd-c50" else "qr", m, n, precision)[0][1]
-        flops = level0_flops(m, n, b, form_q=True)
-        byts = 8.0 * m * n * 2                  # read A, write Q1
-        intensity = flops / byts
-        if intensity > FP64_RIDGE:
-            achieved = flops / (dom_ms_launch * 1e-3) / 1e12
-            roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
-        else:
-            achieved = byts / (dom_ms_launch * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    elif dom == "apply_level0":
-        k = 2 * n if name == "svd-c50" else n
-        flops = 2.0 * m * n * k
-        byts = 8.0 * m * n + 8.0 * m * k        # read Q1, write Q (and U)
-        if flops / byts > FP64_RIDGE:
-            achieved = flops / (dom_ms_launch * 1e-3) / 1e12
-            roof = {"bound": "alu", "achieved": achieved, "peak": FP64_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS, "traffic": None}
-        else:
-            achieved = byts / (dom_ms_launch * 1e-3) / 1e9
-            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS, "traffic": None}
-    else:
-        achieved = alg_bytes / (dom_ms_launch * 1e-3) / 1e9
-        roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": None}
+    plan_op = "svd" if name == "svd-c50" else "qr"
+    roof = roofline(dom, dom_ms_launch, m, n, plan_op, precision, _lib)
     roof["kernel"] = dom
     roof["ms_per_launch"] = dom_ms_launch
 
@@ -191,6 +182,8 @@ def main():
         Rh = R.cpu().numpy()
         normA = oracle.norm2(A_h)
         acc = {"orth": oracle.metric_orth(Qh), "backward": oracle.metric_backward(A_h, Qh, Rh, normA)}
+        if name == "grad-c100":
+            acc["grad_rel_err"] = grad_error(A_h, ct, dA, m)
         if name == "svd-c50":
             acc["svd_backward"] = oracle.metric_svd_backward(A_h, U.cpu().numpy(), S.cpu().numpy(),
                                                              V.cpu().numpy(), normA)
@@ -203,25 +196,69 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(name, A_h, n, sample_rows):
-    """The oracle as it stands, on the first rows of the same workload (bounded sample)."""
-    import oracle
-    cfg = __import__("workloads").CONFIGS[name]
-    threads = oracle.max_threads(0)
-    ms = sample_rows or min(A_h.shape[0], {"svd-c50": 1_000_000, "qr-small": 100_000,
-                                           "mixed-c25": 2_000_000}[name])
-    As = np.ascontiguousarray(A_h[:ms])
-    t0 = time.perf_counter()
-    if name == "svd-c50":
-        oracle.tsqr_svd(As, block_rows=cfg["block_rows"], want_qr=True)
-        byts = 3 * 8.0 * ms * n
+def roofline(dom, ms_launch, m, n, plan_op, precision, _lib):
+    """Roofline entry for one launch of the dominant kernel class: algorithmic flops and bytes of
+    that launch, placed against FP64 peak or HBM bandwidth by their ratio."""
+    if dom == "factor_level0":
+        b = _lib.plan_levels(plan_op, m, n, precision)[0][1]
+        flops, byts = level0_flops(m, n, b, form_q=True), 16.0 * m * n     # read A, write Q1
+    elif dom == "apply_level0":
+        k = 2 * n if plan_op == "svd" else n
+        flops, byts = 2.0 * m * n * k, 8.0 * m * n + 8.0 * m * k          # read Q1, write Q (U)
+    elif dom == "bwd_gemm":
+        flops, byts = 4.0 * m * n * n, 24.0 * m * n                        # read Q, dQ; write dA
+    elif dom == "bwd_gram":
+        flops, byts = 2.0 * m * n * n, 16.0 * m * n                        # read dQ, Q
     else:
-        oracle.tsqr(As, block_rows=cfg["block_rows"])
-        byts = 2 * 8.0 * ms * n
-    dt = time.perf_counter() - t0
-    return {"value": byts / dt / 1e9, "unit": "GB/s", "cores": threads, "kind": "oracle",
-            "sample": "first %d of %d rows, oracle blocks of %d rows, %.2f s" % (
-                ms, A_h.shape[0], cfg["block_rows"], dt)}
+        flops, byts = 0.0, 16.0 * m * n
+    sec = ms_launch * 1e-3
+    if flops / byts > FP64_RIDGE:
+        a = flops / sec / 1e12
+        return {"bound": "alu", "achieved": a, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": a / FP64_PEAK_TFLOPS, "traffic": None}
+    a = byts / sec / 1e9
+    return {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": a / HBM_PEAK_GBS, "traffic": None}
+
+
+def grad_error(A_h, ct, dA, m):
+    """Relative error of dA against the oracle's adjoint on the leading rows: the rows of dA depend
+    on all of A through the Gram dQ^T Q, so the oracle runs on the full input (bounded cost)."""
+    import oracle
+    Qo, Ro = oracle.tsqr(A_h, block_rows=8192)
+    ref = oracle.qr_backward(Qo, Ro, ct["dQ"], ct["dR"])
+    got = dA.cpu().numpy()
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+
+
+def cpu_baseline(name, A_h, n, sample_rows, min_seconds=10.0):
+    """The oracle as it stands, on the leading rows of the same workload, repeated until about
+    ten seconds of CPU work have been timed; reports the mean rate."""
+    import oracle
+    import workloads
+    cfg = workloads.CONFIGS[name]
+    threads = oracle.max_threads(0)
+    default_rows = {"grad-c100": 250_000}.get(name, A_h.shape[0])
+    ms = min(A_h.shape[0], sample_rows or default_rows)
+    As = np.ascontiguousarray(A_h[:ms])
+    ct = workloads.cotangents(ms, n) if name == "grad-c100" else None
+    per_pass = {"svd-c50": 3, "grad-c100": 5}.get(name, 2) * 8.0 * ms * n
+    reps, dt = 0, 0.0
+    while dt < min_seconds:
+        t0 = time.perf_counter()
+        if name == "svd-c50":
+            oracle.tsqr_svd(As, block_rows=cfg["block_rows"], want_qr=True)
+        elif name == "grad-c100":
+            Qo, Ro = oracle.tsqr(As, block_rows=cfg["block_rows"])
+            oracle.qr_backward(Qo, Ro, ct["dQ"], ct["dR"])
+        else:
+            oracle.tsqr(As, block_rows=cfg["block_rows"])
+        dt += time.perf_counter() - t0
+        reps += 1
+    return {"value": per_pass * reps / dt / 1e9, "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": "first %d of %d rows, oracle blocks of %d rows, %d passes in %.1f s" % (
+                ms, A_h.shape[0], cfg["block_rows"], reps, dt)}
 
 
 if __name__ == "__main__":

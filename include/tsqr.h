@@ -118,6 +118,38 @@ tsqr_status tsqr_qr_f32(int64_t m, int64_t n, const float *A, int64_t lda, float
                         const tsqr_opts *opts, void *stream);
 
 /*
+ * Differentiation form: adjoint of tsqr_qr.  For the loss <dQ, Q> + <dR, R> with cotangents dQ
+ * (m x n, lddq; NULL = zero) and dR (n x n, lddr; NULL = zero; only its upper triangle matters,
+ * R's strict lower part being identically zero) writes dA (m x n, ldda).  Q and R are recomputed
+ * from A by the forward kernels, so nothing from a forward call (in particular no Q1_i) needs to
+ * be kept.  Closed form (not in the paper; Walter & Lehmann 2018, Seeger et al. 2017):
+ *     M = R triu(dR)^T - dQ^T Q,   dA = (dQ + Q copyltu(M)) R^{-T},
+ *     copyltu(M) = tril(M) + tril(M, -1)^T.
+ * FP64 only (opts->precision must be TSQR_FP64).  Workspace: tsqr_workspace_bytes with
+ * TSQR_OP_QR_BACKWARD.  d_info as for tsqr_qr, or -3 if R has a zero diagonal entry.
+ */
+tsqr_status tsqr_qr_backward(int64_t m, int64_t n, const double *A, int64_t lda,
+                             const double *dQ, int64_t lddq, const double *dR, int64_t lddr,
+                             double *dA, int64_t ldda, void *ws, size_t ws_bytes,
+                             int32_t *d_info, const tsqr_opts *opts, void *stream);
+
+/*
+ * Adjoint of tsqr_svd (m > n, distinct nonzero singular values): for the loss
+ * <dU, U> + <dS, S> + <dV, V> (each cotangent NULL = zero; dS has n entries) writes dA.  U, S, V
+ * are recomputed from A.  Closed form (Townsend 2016, Ionescu et al. 2015):
+ *     F_ij = 1/(s_j^2 - s_i^2) (i != j), F_ii = 0, J = F o (U^T dU - dU^T U),
+ *     K = F o (V^T dV - dV^T V),
+ *     dA = U (J S + diag(dS) + S K) V^T + (dU - U (U^T dU)) S^{-1} V^T.
+ * The result follows the gauge of tsqr_svd.  d_info as for tsqr_svd, or -3 if two singular
+ * values coincide or one is zero.  Workspace: TSQR_OP_SVD_BACKWARD.
+ */
+tsqr_status tsqr_svd_backward(int64_t m, int64_t n, const double *A, int64_t lda,
+                              const double *dU, int64_t lddu, const double *dS,
+                              const double *dV, int64_t lddv, double *dA, int64_t ldda,
+                              void *ws, size_t ws_bytes, int32_t *d_info,
+                              const tsqr_opts *opts, void *stream);
+
+/*
  * The recursive tree the library runs for `op` on an m x n input (Sec. III-C): level 0 factors A,
  * level L >= 1 the stacked R factors of level L-1.  Writes the number of levels to *nlevels and,
  * for the first max_levels levels, the rows of the level matrix and its panel height (host

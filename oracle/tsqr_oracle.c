@@ -387,10 +387,12 @@ int oracle_qr_backward(int64_t m, int64_t n, const double *Q, int64_t ldq, const
                 M[i * n + j] = acc;
             }
     if (dQ) {
-        /* M -= dQ^T Q, accumulated over rows in long double */
+        /* M -= dQ^T Q, accumulated over rows in long double (threads split the rows i of the
+           product; each entry still sums r = 0, 1, ... in order) */
         long double *acc = calloc((size_t)(n * n), sizeof(long double));
-        for (int64_t r = 0; r < m; ++r)
-            for (int64_t i = 0; i < n; ++i) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t r = 0; r < m; ++r) {
                 long double a = dQ[r * lddq + i];
                 for (int64_t j = 0; j < n; ++j) acc[i * n + j] += a * Q[r * ldq + j];
             }
@@ -440,8 +442,9 @@ int oracle_svd_backward(int64_t m, int64_t n, const double *U, int64_t ldu, cons
     if (!UtdU || !Inner || !B1 || !B2) { free(UtdU); free(Inner); free(B1); free(B2); return ERR_NOMEM; }
     if (dU) {
         long double *acc = calloc((size_t)(n * n), sizeof(long double));
-        for (int64_t r = 0; r < m; ++r)
-            for (int64_t i = 0; i < n; ++i) {
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t r = 0; r < m; ++r) {
                 long double a = U[r * ldu + i];
                 for (int64_t j = 0; j < n; ++j) acc[i * n + j] += a * dU[r * lddu + j];
             }

@@ -3,6 +3,8 @@
 The factorization runs in hand-written HIP kernels inside ``libtsqr.so`` (C ABI in
 ``include/tsqr.h``); this package is the thin Python binding over it.
 """
-from .tsqr import qr, r, svd, workspace_bytes  # noqa: F401
+from .tsqr import (QRFunction, SVDFunction, qr, qr_autograd, qr_backward, r, svd,  # noqa: F401
+                   svd_autograd, svd_backward, workspace_bytes)
 
-__all__ = ["qr", "r", "svd", "workspace_bytes"]
+__all__ = ["qr", "r", "svd", "workspace_bytes", "qr_backward", "svd_backward", "qr_autograd",
+           "svd_autograd", "QRFunction", "SVDFunction"]

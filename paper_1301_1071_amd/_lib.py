@@ -32,6 +32,10 @@ SIGNATURES = {
                            _vp]),
     "tsqr_svd": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
                         _vp, _sz, _vp, _vp, _vp]),
+    "tsqr_qr_backward": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz,
+                                 _vp, _vp, _vp]),
+    "tsqr_svd_backward": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp,
+                                  _sz, _vp, _vp, _vp]),
     "tsqr_plan_levels": (_i32, [_i32, _i64, _i64, _vp, _i32, ctypes.POINTER(_i32),
                                  ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "tsqr_profile_enable": (_i32, [_i32]),

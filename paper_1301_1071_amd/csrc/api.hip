@@ -20,10 +20,11 @@ namespace {
 // ---- optional per-launch timing (benchmarks): HIP event pairs on the launch stream ----------
 enum ProfClass {
     PC_FACTOR0 = 0, PC_FACTOR_TREE, PC_FINALIZE, PC_APPLY_TREE, PC_APPLY0, PC_REFINE,
-    PC_COUNT
+    PC_BWD_GRAM, PC_BWD_SMALL, PC_BWD_GEMM, PC_COUNT
 };
 const char *kProfNames[PC_COUNT] = {"factor_level0", "factor_tree", "finalize_svd",
-                                    "apply_tree", "apply_level0", "refine"};
+                                    "apply_tree", "apply_level0", "refine",
+                                    "bwd_gram", "bwd_small", "bwd_gemm"};
 struct ProfRec { int cls; hipEvent_t a, b; };
 struct Profiler {
     std::mutex mu;
@@ -294,6 +295,41 @@ tsqr_status do_qr(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda
     return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, nullptr, 0, st);
 }
 
+// Backward workspace: the forward plan's workspace, then the recomputed factor and the adjoint
+// scratch.
+struct BwdLayout {
+    Plan fwd;
+    size_t q = 0, r = 0, s = 0, v = 0, part = 0, g = 0, w2 = 0, scratch = 0, total = 0;
+    int nblk = 0;
+};
+
+tsqr_status build_bwd_layout(bool svd, int64_t m, int64_t n, const tsqr_opts *o, BwdLayout &bl)
+{
+    if (o && o->precision != TSQR_FP64) return TSQR_ERR_UNSUPPORTED;
+    tsqr_status s = svd ? build_plan(OP_SVD, m, n, F64, o, false, true, bl.fwd)
+                        : build_plan(OP_QR, m, n, F64, o, true, false, bl.fwd);
+    if (s != TSQR_OK) return s;
+    size_t off = align_up(bl.fwd.total);
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return at;
+    };
+    bl.q = take(sizeof(double) * (size_t)m * n);
+    bl.r = take(sizeof(double) * (size_t)n * n);
+    bl.s = take(sizeof(double) * (size_t)n);
+    bl.v = take(sizeof(double) * (size_t)n * n);
+    bl.nblk = gram_blocks(m);
+    bl.part = take(sizeof(double) * (size_t)bl.nblk * n * n);
+    bl.g = take(sizeof(double) * (size_t)n * n);
+    bl.w2 = take(sizeof(double) * 2 * (size_t)n * n);
+    bl.scratch = take(sizeof(double) * 2 * (size_t)n * n);
+    bl.total = off;
+    return TSQR_OK;
+}
+
+constexpr int kBwdPanel = 256;   // rows per work-group of the backward's tall products
+
 }  // namespace
 }  // namespace tsqr
 
@@ -321,6 +357,14 @@ tsqr_status tsqr_workspace_bytes(int32_t op, int64_t m, int64_t n, const tsqr_op
     case TSQR_OP_R: s = build_plan(OP_R, m, n, F64, o, false, false, pl); break;
     case TSQR_OP_QR: s = build_plan(OP_QR, m, n, F64, o, true, false, pl); break;
     case TSQR_OP_SVD: s = build_plan(OP_SVD, m, n, F64, o, true, true, pl); break;
+    case TSQR_OP_QR_BACKWARD:
+    case TSQR_OP_SVD_BACKWARD: {
+        BwdLayout bl;
+        s = build_bwd_layout(op == TSQR_OP_SVD_BACKWARD, m, n, o, bl);
+        if (s != TSQR_OK) return s;
+        *bytes = bl.total;
+        return TSQR_OK;
+    }
     default: return TSQR_ERR_INVALID_ARG;
     }
     if (s != TSQR_OK) return s;
@@ -407,6 +451,96 @@ tsqr_status tsqr_plan_levels(int32_t op, int64_t m, int64_t n, const tsqr_opts *
         rows[L] = pl.lev[L].rows;
         panel_rows[L] = pl.lev[L].b;
     }
+    return TSQR_OK;
+}
+
+tsqr_status tsqr_qr_backward(int64_t m, int64_t n, const double *A, int64_t lda,
+                             const double *dQ, int64_t lddq, const double *dR, int64_t lddr,
+                             double *dA, int64_t ldda, void *ws, size_t ws_bytes,
+                             int32_t *d_info, const tsqr_opts *opts, void *stream)
+{
+    if (!A || !dA || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldda < n || (dQ && lddq < n) || (dR && lddr < n)) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    const tsqr_opts *o = opts_or_default(opts, tmp);
+    BwdLayout bl;
+    tsqr_status s = build_bwd_layout(false, m, n, o, bl);
+    if (s != TSQR_OK) return s;
+    if (!ws || ws_bytes < bl.total) return TSQR_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double *Q = (double *)wsp(ws, bl.q), *R = (double *)wsp(ws, bl.r);
+    double *W2 = (double *)wsp(ws, bl.w2);
+    // recompute Q and R from A (the forward kernels; Q1_i is never kept across calls)
+    if ((s = run_factor_levels(bl.fwd, A, lda, ws, st)) != TSQR_OK) return s;
+    {
+        ProfScope ps(PC_FINALIZE, st);
+        TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, bl.fwd.lev[bl.fwd.nlev - 1].s), R,
+                                       nullptr, n, (double *)wsp(ws, bl.fwd.wtop), bl.fwd.k, 1, 0,
+                                       nullptr, nullptr, 0, nullptr, nullptr, d_info, st));
+    }
+    if ((s = run_apply_levels(bl.fwd, ws, F64, Q, n, (int)n, nullptr, 0, st)) != TSQR_OK) return s;
+    if (dQ) {
+        ProfScope ps(PC_BWD_GRAM, st);
+        TSQR_HIP_CHECK(launch_gram(m, n, dQ, lddq, Q, n, (double *)wsp(ws, bl.part),
+                                   (double *)wsp(ws, bl.g), st));
+    }
+    {
+        ProfScope ps(PC_BWD_SMALL, st);
+        TSQR_HIP_CHECK(launch_qr_bwd_small(n, R, dR, lddr, dQ ? (double *)wsp(ws, bl.g) : nullptr,
+                                           W2, (double *)wsp(ws, bl.scratch), d_info, st));
+    }
+    ProfScope ps(PC_BWD_GEMM, st);
+    TSQR_HIP_CHECK(launch_gemm_mfma(F64, F64, m, n, kBwdPanel, Q, n, W2 + n * n, n, 0, (int)n, dA,
+                                    ldda, (int)n, nullptr, 0, 0, st));
+    if (dQ)
+        TSQR_HIP_CHECK(launch_gemm_mfma(F64, F64, m, n, kBwdPanel, dQ, lddq, W2, n, 0, (int)n, dA,
+                                        ldda, (int)n, nullptr, 0, 1, st));
+    return TSQR_OK;
+}
+
+tsqr_status tsqr_svd_backward(int64_t m, int64_t n, const double *A, int64_t lda,
+                              const double *dU, int64_t lddu, const double *dS,
+                              const double *dV, int64_t lddv, double *dA, int64_t ldda,
+                              void *ws, size_t ws_bytes, int32_t *d_info,
+                              const tsqr_opts *opts, void *stream)
+{
+    if (!A || !dA || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldda < n || (dU && lddu < n) || (dV && lddv < n)) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    const tsqr_opts *o = opts_or_default(opts, tmp);
+    BwdLayout bl;
+    tsqr_status s = build_bwd_layout(true, m, n, o, bl);
+    if (s != TSQR_OK) return s;
+    if (!ws || ws_bytes < bl.total) return TSQR_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double *U = (double *)wsp(ws, bl.q), *S = (double *)wsp(ws, bl.s), *V = (double *)wsp(ws, bl.v);
+    double *W2 = (double *)wsp(ws, bl.w2);
+    if ((s = run_factor_levels(bl.fwd, A, lda, ws, st)) != TSQR_OK) return s;
+    {
+        ProfScope ps(PC_FINALIZE, st);
+        TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, bl.fwd.lev[bl.fwd.nlev - 1].s),
+                                       nullptr, nullptr, 0, (double *)wsp(ws, bl.fwd.wtop),
+                                       bl.fwd.k, 0, 1, S, V, n, (double *)wsp(ws, bl.fwd.svd_g),
+                                       (double *)wsp(ws, bl.fwd.svd_v), d_info, st));
+    }
+    if ((s = run_apply_levels(bl.fwd, ws, F64, U, n, (int)n, nullptr, 0, st)) != TSQR_OK) return s;
+    if (dU) {
+        ProfScope ps(PC_BWD_GRAM, st);
+        TSQR_HIP_CHECK(launch_gram(m, n, U, n, dU, lddu, (double *)wsp(ws, bl.part),
+                                   (double *)wsp(ws, bl.g), st));
+    }
+    {
+        ProfScope ps(PC_BWD_SMALL, st);
+        TSQR_HIP_CHECK(launch_svd_bwd_small(n, S, V, dS, dV, lddv,
+                                            dU ? (double *)wsp(ws, bl.g) : nullptr, W2,
+                                            (double *)wsp(ws, bl.scratch), d_info, st));
+    }
+    ProfScope ps(PC_BWD_GEMM, st);
+    TSQR_HIP_CHECK(launch_gemm_mfma(F64, F64, m, n, kBwdPanel, U, n, W2, n, 0, (int)n, dA, ldda,
+                                    (int)n, nullptr, 0, 0, st));
+    if (dU)
+        TSQR_HIP_CHECK(launch_gemm_mfma(F64, F64, m, n, kBwdPanel, dU, lddu, W2 + n * n, n, 0,
+                                        (int)n, dA, ldda, (int)n, nullptr, 0, 1, st));
     return TSQR_OK;
 }
 

@@ -38,9 +38,10 @@ constexpr int kWaves = 4;
 
 template <typename T, typename To, int NT>
 __global__ void __launch_bounds__(kWaves * 64)
-k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, const double *__restrict__ W,
-             int64_t ldw, int64_t wstride, int k, To *__restrict__ out0, int64_t ld0, int k0,
-             To *__restrict__ out1, int64_t ld1)
+k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, int64_t ldq,
+             const double *__restrict__ W, int64_t ldw, int64_t wstride, int k,
+             To *__restrict__ out0, int64_t ld0, int k0, To *__restrict__ out1, int64_t ld1,
+             int accumulate)
 {
     typedef typename Mfma<T>::acc_t acc_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -72,10 +73,10 @@ k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, const double 
     for (int blk = w; blk < nblk; blk += kWaves) {
         const int r0 = blk * 16;
         const int cnt = min(16, nr - r0);
-        const T *src = q1 + (rb + r0) * n;
+        const T *src = q1 + (rb + r0) * ldq;
         for (int e = lane; e < 16 * n; e += 64) {
             const int r = e / n, c = e - r * n;
-            as[r * LDA + c] = (r < cnt) ? src[e] : T(0);
+            as[r * LDA + c] = (r < cnt) ? src[(int64_t)r * ldq + c] : T(0);
         }
         // the wave reads back what its own lanes wrote: LDS operations of a wave are ordered
         acc_t acc[NT];
@@ -95,8 +96,13 @@ k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, const double 
                 const int r = Mfma<T>::row(lane, i);
                 if (r < cnt) {
                     const int64_t gr = rb + r0 + r;
-                    if (j < k0) out0[gr * ld0 + j] = (To)acc[t][i];
-                    else if (j < k) out1[gr * ld1 + (j - k0)] = (To)acc[t][i];
+                    if (j < k0) {
+                        To *o = out0 + gr * ld0 + j;
+                        *o = accumulate ? (To)(acc[t][i] + (T)*o) : (To)acc[t][i];
+                    } else if (j < k) {
+                        To *o = out1 + gr * ld1 + (j - k0);
+                        *o = accumulate ? (To)(acc[t][i] + (T)*o) : (To)acc[t][i];
+                    }
                 }
             }
         }
@@ -104,9 +110,9 @@ k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, const double 
 }
 
 template <typename T, typename To, int NT>
-hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, const double *W,
-                         int64_t ldw, int64_t wstride, int k, void *out0, int64_t ld0, int k0,
-                         void *out1, int64_t ld1, hipStream_t st)
+hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t ldq,
+                         const double *W, int64_t ldw, int64_t wstride, int k, void *out0,
+                         int64_t ld0, int k0, void *out1, int64_t ld1, int acc, hipStream_t st)
 {
     const int KC = (int)((n + 3) / 4);
     const size_t lds = sizeof(T) * ((size_t)KC * NT * 64 + (size_t)kWaves * 16 * (4 * KC + 1));
@@ -120,43 +126,59 @@ hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, const d
     }
     const int64_t panels = ceil_div(rows, b);
     dim3 grid((unsigned)panels, (unsigned)ceil_div(k, 16 * NT));
-    hipLaunchKernelGGL(kern, grid, dim3(kWaves * 64), lds, st, rows, (int)n, b, (const T *)q1, W,
-                       ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1, ld1);
+    hipLaunchKernelGGL(kern, grid, dim3(kWaves * 64), lds, st, rows, (int)n, b, (const T *)q1,
+                       ldq, W, ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1, ld1, acc);
     return hipGetLastError();
 }
 
 template <typename T, typename To>
-hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, const double *W,
-                        int64_t ldw, int64_t wstride, int k, void *out0, int64_t ld0, int k0,
-                        void *out1, int64_t ld1, hipStream_t st)
+hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t ldq,
+                        const double *W, int64_t ldw, int64_t wstride, int k, void *out0,
+                        int64_t ld0, int k0, void *out1, int64_t ld1, int acc, hipStream_t st)
 {
     // one pass covers up to 16 * NT output columns; NT = 8 keeps W's LDS image <= 128 KiB
     const int tiles = (int)ceil_div(k, 16);
+#define TSQR_NT(NT)                                                                          \
+    return apply_mfma_nt<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1, \
+                                    ld1, acc, st)
     // FP64 with n > 64: W's LDS image is capped at 4 tiles per pass (LDS stays under 140 KiB)
-    if (sizeof(T) == 8 && n > 64 && tiles > 2)
-        return apply_mfma_nt<T, To, 4>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
-    if (tiles <= 2) return apply_mfma_nt<T, To, 2>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
-    if (tiles <= 4) return apply_mfma_nt<T, To, 4>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
-    if (tiles <= 7) return apply_mfma_nt<T, To, 7>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
-    return apply_mfma_nt<T, To, 8>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
+    if (sizeof(T) == 8 && n > 64 && tiles > 2) TSQR_NT(4);
+    if (tiles <= 2) TSQR_NT(2);
+    if (tiles <= 4) TSQR_NT(4);
+    if (tiles <= 7) TSQR_NT(7);
+    TSQR_NT(8);
+#undef TSQR_NT
 }
 
 }  // namespace
+
+hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
+                            const void *q1, int64_t ldq, const double *W, int64_t ldw,
+                            int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
+                            int64_t ld1, int accumulate, hipStream_t st)
+{
+    if (n > 4 * kMaxKC) return hipErrorInvalidValue;
+    if (q_dtype == F64) {
+        if (out_dtype == F64)
+            return apply_mfma_t<double, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0,
+                                                k0, out1, ld1, accumulate, st);
+        return apply_mfma_t<double, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
+                                           out1, ld1, accumulate, st);
+    }
+    if (out_dtype == F64)
+        return apply_mfma_t<float, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
+                                           out1, ld1, accumulate, st);
+    return apply_mfma_t<float, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1,
+                                      ld1, accumulate, st);
+}
 
 hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                              const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
                              void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
                              hipStream_t st)
 {
-    if (n > 4 * kMaxKC) return hipErrorInvalidValue;
-    if (q_dtype == F64) {
-        if (out_dtype == F64)
-            return apply_mfma_t<double, double>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
-        return apply_mfma_t<double, float>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
-    }
-    if (out_dtype == F64)
-        return apply_mfma_t<float, double>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
-    return apply_mfma_t<float, float>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1, st);
+    return launch_gemm_mfma(q_dtype, out_dtype, rows, n, b, q1, n, W, ldw, wstride, k, out0, ld0,
+                            k0, out1, ld1, 0, st);
 }
 
 }  // namespace tsqr

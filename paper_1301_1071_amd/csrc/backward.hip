@@ -1,0 +1,215 @@
+// Differentiation form: the closed-form adjoints of the thin QR and thin SVD (not in the paper;
+// Walter & Lehmann 2018 / Seeger et al. 2017 for QR, Townsend 2016 / Ionescu et al. 2015 for the
+// SVD), evaluated with the forward kernels recomputing Q (or U) from A.
+//   QR:  M = R triu(dR)^T - dQ^T Q,  dA = (dQ + Q copyltu(M)) R^{-T}
+//        = [dQ, Q] [R^{-T}; copyltu(M) R^{-T}]
+//   SVD: F_ij = 1/(s_j^2 - s_i^2) (i != j), J = F o (U^T dU - dU^T U), K = F o (V^T dV - dV^T V),
+//        dA = U (J S + diag(dS) + S K) V^T + (dU - U U^T dU) S^{-1} V^T
+//           = [U, dU] [(J S + diag(dS) + S K - (U^T dU) S^{-1}) V^T; S^{-1} V^T]
+// The tall products run on the MFMA GEMM; this file holds the n x n middle steps and the Gram
+// reduction dQ^T Q (U^T dU) over the m rows.
+#include "tsqr_internal.h"
+
+namespace tsqr {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kGramMaxBlocks = 512;
+constexpr int kGramTiles = 8;     // n <= 128
+
+// Partial Gram of one row block on the matrix cores: C_b = X_b^T Y_b.  Wave w owns the 16-column
+// strips mt = w, w+4, ... of X and all strips of Y; v_mfma_f64_16x16x4 contracts 4 rows at a time
+// with A = X^T (lane l: X[r + l/16][16 mt + l%16]) and B = Y (lane l: Y[r + l/16][16 nt + l%16]).
+__global__ void __launch_bounds__(256)
+k_gram(int64_t m, int n, const double *__restrict__ X, int64_t ldx, const double *__restrict__ Y,
+       int64_t ldy, int64_t rows_per_block, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63;
+    const int w = threadIdx.x >> 6;
+    const int T = (n + 15) >> 4;
+    const int64_t r_begin = (int64_t)blockIdx.x * rows_per_block;
+    const int64_t r_end = min(m, r_begin + rows_per_block);
+    const int cx = lane & 15, rq = lane >> 4;
+    double *out = part + (int64_t)blockIdx.x * n * n;
+    for (int mt = w; mt < T; mt += 4) {
+        d4_t acc[kGramTiles];
+#pragma unroll
+        for (int t = 0; t < kGramTiles; ++t) acc[t] = d4_t{0, 0, 0, 0};
+        const int ca = 16 * mt + cx;
+        for (int64_t r = r_begin; r < r_end; r += 4) {
+            const int64_t rr = r + rq;
+            const bool rin = rr < r_end;
+            const double a = (rin && ca < n) ? X[rr * ldx + ca] : 0.0;
+#pragma unroll
+            for (int t = 0; t < kGramTiles; ++t) {
+                if (t < T) {
+                    const int cb = 16 * t + cx;
+                    const double b = (rin && cb < n) ? Y[rr * ldy + cb] : 0.0;
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kGramTiles; ++t) {
+            if (t < T) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int row = 16 * mt + rq + 4 * i, col = 16 * t + cx;   // f64 result layout
+                    if (row < n && col < n) out[(int64_t)row * n + col] = acc[t][i];
+                }
+            }
+        }
+    }
+}
+
+// G = sum of the partial Grams, in block order (one thread per entry)
+__global__ void __launch_bounds__(256)
+k_gram_sum(int64_t nn, const double *__restrict__ part, int nblk, double *__restrict__ G)
+{
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nn) return;
+    double a = 0.0;
+    for (int b = 0; b < nblk; ++b) a += part[(int64_t)b * nn + e];
+    G[e] = a;
+}
+
+// Rinv = R^{-1} (R upper triangular, n x n): thread j solves R x = e_j by back substitution.
+__device__ void tri_inverse(int n, const double *R, double *Rinv)
+{
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        for (int i = n - 1; i > j; --i) Rinv[i * n + j] = 0.0;
+        for (int i = j; i >= 0; --i) {
+            double acc = (i == j) ? 1.0 : 0.0;
+            for (int t = i + 1; t <= j; ++t) acc = fma(-R[i * n + t], Rinv[t * n + j], acc);
+            Rinv[i * n + j] = acc / R[i * n + i];
+        }
+    }
+}
+
+// G = dQ^T Q (NULL: dQ = 0); scratch (2 n^2): Rinv, C
+__global__ void __launch_bounds__(1024)
+k_qr_bwd_small(int n, const double *__restrict__ R, const double *__restrict__ dR, int64_t lddr,
+               const double *__restrict__ G, double *__restrict__ W2,
+               double *__restrict__ scratch, int32_t *__restrict__ info)
+{
+    double *Rinv = scratch, *C = scratch + (size_t)n * n;
+    const int tid = threadIdx.x;
+    tri_inverse(n, R, Rinv);
+    __syncthreads();
+    // M = R triu(dR)^T - G, then C = copyltu(M) (lower triangle mirrored up)
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        if (j > i) continue;
+        double mij = 0.0, mji = 0.0;
+        if (dR) {
+            for (int k = j; k < n; ++k) mij = fma(R[i * n + k], dR[(int64_t)j * lddr + k], mij);
+            (void)mji;
+        }
+        if (G) mij -= G[i * n + j];
+        C[i * n + j] = mij;
+        C[j * n + i] = mij;
+    }
+    __syncthreads();
+    // W2 = [R^{-T}; C R^{-T}]
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        W2[(int64_t)i * n + j] = Rinv[j * n + i];
+        double acc = 0.0;
+        for (int t = j; t < n; ++t) acc = fma(C[i * n + t], Rinv[j * n + t], acc);
+        W2[(int64_t)(n + i) * n + j] = acc;
+    }
+    if (tid == 0) {
+        int bad = 0;
+        for (int i = 0; i < n; ++i) bad |= !(R[i * n + i] != 0.0);
+        if (bad) *info = -3;
+    }
+}
+
+// UtdU = U^T dU (NULL: dU = 0); scratch (2 n^2): VtdV, T1
+__global__ void __launch_bounds__(1024)
+k_svd_bwd_small(int n, const double *__restrict__ S, const double *__restrict__ V,
+                const double *__restrict__ dS, const double *__restrict__ dV, int64_t lddv,
+                const double *__restrict__ UtdU, double *__restrict__ W2,
+                double *__restrict__ scratch, int32_t *__restrict__ info)
+{
+    double *VtdV = scratch, *T1 = scratch + (size_t)n * n;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        double acc = 0.0;
+        if (dV)
+            for (int k = 0; k < n; ++k) acc = fma(V[k * n + i], dV[(int64_t)k * lddv + j], acc);
+        VtdV[e] = acc;
+    }
+    __syncthreads();
+    // T1 = J S + diag(dS) + S K - (U^T dU) S^{-1}
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        const double F = (i == j) ? 0.0 : 1.0 / (S[j] * S[j] - S[i] * S[i]);
+        const double uij = UtdU ? UtdU[i * n + j] : 0.0, uji = UtdU ? UtdU[j * n + i] : 0.0;
+        const double Jij = F * (uij - uji);
+        const double Kij = F * (VtdV[i * n + j] - VtdV[j * n + i]);
+        double v = Jij * S[j] + S[i] * Kij - uij / S[j];
+        if (i == j && dS) v += dS[i];
+        T1[e] = v;
+    }
+    __syncthreads();
+    // W2 = [T1 V^T; S^{-1} V^T]
+    for (int e = tid; e < n * n; e += blockDim.x) {
+        const int i = e / n, j = e - i * n;
+        double acc = 0.0;
+        for (int t = 0; t < n; ++t) acc = fma(T1[i * n + t], V[j * n + t], acc);
+        W2[(int64_t)i * n + j] = acc;
+        W2[(int64_t)(n + i) * n + j] = V[j * n + i] / S[i];
+    }
+    if (tid == 0) {
+        int bad = 0;
+        for (int i = 0; i < n; ++i) {
+            bad |= !(S[i] > 0.0);
+            if (i > 0) bad |= !(S[i - 1] != S[i]);
+        }
+        if (bad) *info = -3;
+    }
+}
+
+}  // namespace
+
+int gram_blocks(int64_t m)
+{
+    int64_t b = ceil_div(m, 2048);
+    return (int)(b < 1 ? 1 : (b > kGramMaxBlocks ? kGramMaxBlocks : b));
+}
+
+hipError_t launch_gram(int64_t m, int64_t n, const double *X, int64_t ldx, const double *Y,
+                       int64_t ldy, double *part, double *G, hipStream_t st)
+{
+    if (n > 16 * kGramTiles) return hipErrorInvalidValue;
+    const int nb = gram_blocks(m);
+    const int64_t rpb = (ceil_div(m, nb) + 3) / 4 * 4;
+    hipLaunchKernelGGL(k_gram, dim3(nb), dim3(256), 0, st, m, (int)n, X, ldx, Y, ldy, rpb, part);
+    const int64_t nn = n * n;
+    hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, st, nn, part,
+                       nb, G);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_bwd_small(int64_t n, const double *R, const double *dR, int64_t lddr,
+                               const double *G, double *W2, double *scratch, int32_t *info,
+                               hipStream_t st)
+{
+    hipLaunchKernelGGL(k_qr_bwd_small, dim3(1), dim3(1024), 0, st, (int)n, R, dR, lddr, G, W2,
+                       scratch, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_svd_bwd_small(int64_t n, const double *S, const double *V, const double *dS,
+                                const double *dV, int64_t lddv, const double *UtdU, double *W2,
+                                double *scratch, int32_t *info, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_svd_bwd_small, dim3(1), dim3(1024), 0, st, (int)n, S, V, dS, dV, lddv,
+                       UtdU, W2, scratch, info);
+    return hipGetLastError();
+}
+
+}  // namespace tsqr

@@ -89,6 +89,25 @@ hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n
                              void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
                              hipStream_t st);
 
+// General tall product on the same kernel: out = X * W (X: rows x n, row stride ldq) panel by
+// panel (panel p of b rows uses W rows [p*wstride, +n)); accumulate != 0 adds to out.
+hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
+                            const void *q1, int64_t ldq, const double *W, int64_t ldw,
+                            int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
+                            int64_t ld1, int accumulate, hipStream_t st);
+
+// ---- launchers (backward.hip) ----------------------------------------------------------------
+// Partial Grams C_b = X_b^T Y_b of row blocks (X, Y: m x n FP64) into part (nblk x n x n).
+int gram_blocks(int64_t m);
+hipError_t launch_gram(int64_t m, int64_t n, const double *X, int64_t ldx, const double *Y,
+                       int64_t ldy, double *part, double *G, hipStream_t st);
+hipError_t launch_qr_bwd_small(int64_t n, const double *R, const double *dR, int64_t lddr,
+                               const double *G, double *W2, double *scratch, int32_t *info,
+                               hipStream_t st);
+hipError_t launch_svd_bwd_small(int64_t n, const double *S, const double *V, const double *dS,
+                                const double *dV, int64_t lddv, const double *UtdU, double *W2,
+                                double *scratch, int32_t *info, hipStream_t st);
+
 // ---- launchers (small.hip) -----------------------------------------------------------------
 // Top of the tree: R = D Rt (D = diag(sign(Rt_jj)), sign(0) = +1) written to R (FP64, ldr) or Rf
 // (FP32, ldr); W_top (n x k) = [D | D U_R] (Q columns first if want_q, then U columns if want_u);

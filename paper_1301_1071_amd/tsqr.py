@@ -53,7 +53,9 @@ def _info_check(info: torch.Tensor, check_info: bool, where: str) -> None:
         if v != 0:
             raise torch.linalg.LinAlgError("%s: info = %d (%s)" % (
                 where, v, "non-finite input" if v == -1 else
-                ("refinement breakdown" if v == -2 else "R[%d][%d] == 0 (rank deficient)" % (v - 1, v - 1))))
+                "refinement breakdown" if v == -2 else
+                "adjoint undefined (zero pivot or repeated singular value)" if v == -3 else
+                "R[%d][%d] == 0 (rank deficient)" % (v - 1, v - 1)))
 
 
 def r(A: torch.Tensor, panel_rows: int = 0, ws: torch.Tensor | None = None,
@@ -127,3 +129,105 @@ def svd(A: torch.Tensor, want_qr: bool = False, panel_rows: int = 0,
 def _svd_ws_bytes(m, n, want_qr, panel_rows):
     # the workspace query reports the SVD plan with Q and U both carried (the larger case)
     return workspace_bytes("svd", m, n, "fp64", panel_rows)
+
+
+def _cotangent(x, shape, A):
+    if x is None:
+        return None
+    if tuple(x.shape) != shape:
+        raise ValueError("cotangent of shape %s, expected %s" % (tuple(x.shape), shape))
+    if x.device != A.device or x.dtype != torch.float64:
+        raise TypeError("cotangents must be float64 tensors on A's device")
+    return x if x.stride(-1) == 1 else x.contiguous()
+
+
+def qr_backward(A: torch.Tensor, dQ: torch.Tensor | None, dR: torch.Tensor | None,
+                ws: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                check_info: bool = True) -> torch.Tensor:
+    """dA for the loss <dQ, Q> + <dR, R> of (Q, R) = qr(A); Q and R are recomputed from A on the
+    GPU (the forward's Q1_i are not kept).  FP64 only."""
+    _require_gpu_matrix(A)
+    m, n = A.shape
+    dQ = _cotangent(dQ, (m, n), A)
+    dR = _cotangent(dR, (n, n), A)
+    dA = torch.empty((m, n), dtype=A.dtype, device=A.device) if out is None else out
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    o = make_opts("fp64", 0)
+    if ws is None:
+        ws = _workspace("qr_backward", m, n, "fp64", 0, A.device)
+    check(lib().tsqr_qr_backward(m, n, _p(A), A.stride(0), _p(dQ), dQ.stride(0) if dQ is not None
+                                 else 0, _p(dR), dR.stride(0) if dR is not None else 0, _p(dA),
+                                 dA.stride(0), _p(ws), ws.numel(), _p(info), ctypes.byref(o),
+                                 _stream(A.device)), "tsqr_qr_backward")
+    _info_check(info, check_info, "tsqr_qr_backward")
+    return dA
+
+
+def svd_backward(A: torch.Tensor, dU: torch.Tensor | None, dS: torch.Tensor | None,
+                 dV: torch.Tensor | None, ws: torch.Tensor | None = None,
+                 out: torch.Tensor | None = None, check_info: bool = True) -> torch.Tensor:
+    """dA for the loss <dU, U> + <dS, S> + <dV, V> of (U, S, V) = svd(A); U, S and V are
+    recomputed from A on the GPU.  FP64 only; the singular values must be distinct and nonzero."""
+    _require_gpu_matrix(A)
+    m, n = A.shape
+    dU = _cotangent(dU, (m, n), A)
+    dS = _cotangent(dS, (n,), A)
+    dV = _cotangent(dV, (n, n), A)
+    dA = torch.empty((m, n), dtype=A.dtype, device=A.device) if out is None else out
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    o = make_opts("fp64", 0)
+    if ws is None:
+        ws = _workspace("svd_backward", m, n, "fp64", 0, A.device)
+    check(lib().tsqr_svd_backward(m, n, _p(A), A.stride(0), _p(dU), dU.stride(0) if dU is not None
+                                  else 0, _p(dS), _p(dV), dV.stride(0) if dV is not None else 0,
+                                  _p(dA), dA.stride(0), _p(ws), ws.numel(), _p(info),
+                                  ctypes.byref(o), _stream(A.device)), "tsqr_svd_backward")
+    _info_check(info, check_info, "tsqr_svd_backward")
+    return dA
+
+
+def _row_major(A):
+    return A if A.stride(1) == 1 else A.contiguous()
+
+
+class QRFunction(torch.autograd.Function):
+    """(Q, R) = qr(A) with the adjoint of tsqr_qr_backward.  Only A is saved: Q1_i is recomputed
+    in the backward rather than held in HBM between the passes."""
+
+    @staticmethod
+    def forward(ctx, A):
+        A = _row_major(A)
+        Q, R = qr(A)
+        ctx.save_for_backward(A)
+        return Q, R
+
+    @staticmethod
+    def backward(ctx, dQ, dR):
+        (A,) = ctx.saved_tensors
+        return qr_backward(A, dQ, dR)
+
+
+class SVDFunction(torch.autograd.Function):
+    """(U, S, V) = svd(A) with the adjoint of tsqr_svd_backward; only A is saved."""
+
+    @staticmethod
+    def forward(ctx, A):
+        A = _row_major(A)
+        U, S, V = svd(A)
+        ctx.save_for_backward(A)
+        return U, S, V
+
+    @staticmethod
+    def backward(ctx, dU, dS, dV):
+        (A,) = ctx.saved_tensors
+        return svd_backward(A, dU, dS, dV)
+
+
+def qr_autograd(A: torch.Tensor):
+    """Differentiable thin QR by direct TSQR (FP64)."""
+    return QRFunction.apply(A)
+
+
+def svd_autograd(A: torch.Tensor):
+    """Differentiable thin SVD by direct TSQR (FP64)."""
+    return SVDFunction.apply(A)

@@ -57,6 +57,14 @@ def test_workspace_query():
     assert _ws("qr", 0, 10)[0] == 1
     assert _ws("qr", 1000, 0)[0] == 1
     assert lib().tsqr_workspace_bytes(9, 10, 1, None, ctypes.byref(ctypes.c_size_t())) == 1
+    # the adjoints hold the forward's workspace plus the recomputed Q (or U) and n x n partials
+    st, bq = _ws("qr_backward", 100_000, 10)
+    assert st == 0 and bq >= b1 + 100_000 * 10 * 8
+    st, bsv = _ws("svd_backward", 100_000, 10)
+    assert st == 0 and bsv >= 100_000 * 10 * 8
+    assert _ws("qr_backward", 1000, 129)[0] == 2
+    assert _ws("svd_backward", 5, 10)[0] == 2
+    assert _ws("qr_backward", 1000, 10, make_opts("fp32"))[0] == 4      # FP64 only
 
 
 def test_opts_validation():
@@ -109,6 +117,24 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     # f32 twins
     assert L.tsqr_qr_f32(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 16, info, None, None) == 3
     assert L.tsqr_r_f32(5, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, None, None) == 2
+    # adjoints: NULL input / output, bad ld, shape, workspace, precision
+    assert L.tsqr_qr_backward(100, 10, None, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30,
+                              info, None, None) == 1
+    assert L.tsqr_qr_backward(100, 10, FAKE, 10, FAKE, 9, FAKE, 10, FAKE, 10, FAKE, 1 << 30,
+                              info, None, None) == 1
+    assert L.tsqr_qr_backward(5, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30,
+                              info, None, None) == 2
+    assert L.tsqr_qr_backward(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 16,
+                              info, None, None) == 3
+    o32 = make_opts("fp32")
+    assert L.tsqr_qr_backward(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30,
+                              info, ctypes.byref(o32), None) == 4
+    assert L.tsqr_svd_backward(100, 10, FAKE, 10, FAKE, 10, FAKE, FAKE, 10, None, 10, FAKE,
+                               1 << 30, info, None, None) == 1
+    assert L.tsqr_svd_backward(100, 10, FAKE, 10, FAKE, 10, FAKE, FAKE, 9, FAKE, 10, FAKE,
+                               1 << 30, info, None, None) == 1
+    assert L.tsqr_svd_backward(100, 10, FAKE, 10, FAKE, 10, FAKE, FAKE, 10, FAKE, 10, FAKE,
+                               16, info, None, None) == 3
 
 
 def test_plan_terminates_for_every_width():
