@@ -149,6 +149,60 @@ tsqr_status tsqr_svd_backward(int64_t m, int64_t n, const double *A, int64_t lda
                               void *ws, size_t ws_bytes, int32_t *d_info,
                               const tsqr_opts *opts, void *stream);
 
+/* ------------------------------------------------------------------------------------------
+ * Batched form: many independent tall-skinny QRs (each by direct TSQR, Sec. III-B/III-C) in one
+ * fixed launch sequence.  Not in the paper: its map tasks factor row blocks of ONE matrix; here
+ * the panels of every matrix of the batch share the same launches.
+ *
+ * A plan is built once on the host for the shapes (m_i, n_i, 1 <= n_i <= 64, m_i >= n_i) and
+ * leading dimensions of the batch; creating it allocates and fills a small device table (the
+ * only allocation and host-device copy of the batched form), so create plans outside any graph
+ * capture.  tsqr_qr_batched then only enqueues kernels (no allocation, memset or host
+ * synchronisation): capturing one call in a HIP graph gives one graph launch for the batch.
+ * ------------------------------------------------------------------------------------------ */
+typedef struct tsqr_batch_plan_t *tsqr_batch_plan;
+
+typedef enum { TSQR_DTYPE_F64 = 0, TSQR_DTYPE_F32 = 1 } tsqr_dtype;
+
+/*
+ * m, n, lda, ldq, ldr: HOST arrays of `batch` entries (row-major leading dimensions of A_i, Q_i,
+ * R_i).  dtype: element type of A, Q and R (TSQR_DTYPE_F32 runs FP32 panels and GEMM with the
+ * FP64 tree of TSQR_FP32).  opts may be NULL; opts->precision must match dtype (TSQR_FP64 or
+ * TSQR_FP32); opts->panel_rows = 0 takes each width's panel height from the tune table
+ * (tsqr_tune_set), otherwise it must equal one of the heights tsqr_tune_variants lists for
+ * every width in the batch.  The plan belongs to the device current at creation.
+ */
+tsqr_status tsqr_batch_plan_create(int32_t batch, const int64_t *m, const int64_t *n,
+                                   const int64_t *lda, const int64_t *ldq, const int64_t *ldr,
+                                   int32_t dtype, const tsqr_opts *opts, tsqr_batch_plan *plan);
+tsqr_status tsqr_batch_plan_destroy(tsqr_batch_plan plan);
+/* Workspace the plan needs (about the bytes of all A_i plus the stacked-R trees). */
+tsqr_status tsqr_batch_workspace_bytes(tsqr_batch_plan plan, size_t *bytes);
+/* Number of kernel launches one tsqr_qr_batched call enqueues. */
+tsqr_status tsqr_batch_plan_launches(tsqr_batch_plan plan, int32_t *nlaunches);
+
+/*
+ * Factor every A_i = Q_i R_i.  d_A, d_Q, d_R: DEVICE arrays of `batch` device pointers (element
+ * type per the plan).  d_info: DEVICE array of `batch` int32, entry i as d_info of tsqr_qr.
+ * Matrices must not overlap their outputs.
+ */
+tsqr_status tsqr_qr_batched(tsqr_batch_plan plan, const void *const *d_A, void *const *d_Q,
+                            void *const *d_R, void *ws, size_t ws_bytes, int32_t *d_info,
+                            void *stream);
+
+/*
+ * Panel-height table used by batched plans, one entry per (dtype, width class n <= 4, 8, 16,
+ * 32, 64).  Each class has up to three register-panel variants (0 = default height, 1 and 2 =
+ * half height with half the rows per lane or half the waves); tsqr_tune_variants lists their
+ * heights for width n (0 = not usable: a panel must hold at least 3n rows).  The autotuner
+ * (paper_1301_1071_amd/autotune.py) times them and records its choice with tsqr_tune_set.
+ * Set the table before creating plans; it is process-wide.
+ */
+tsqr_status tsqr_tune_set(int32_t dtype, int64_t n, int32_t variant);
+tsqr_status tsqr_tune_get(int32_t dtype, int64_t n, int32_t *variant, int32_t *panel_rows);
+tsqr_status tsqr_tune_variants(int32_t dtype, int64_t n, int32_t max, int32_t *panel_rows,
+                               int32_t *count);
+
 /*
  * The recursive tree the library runs for `op` on an m x n input (Sec. III-C): level 0 factors A,
  * level L >= 1 the stacked R factors of level L-1.  Writes the number of levels to *nlevels and,

@@ -36,6 +36,14 @@ SIGNATURES = {
                                  _vp, _vp, _vp]),
     "tsqr_svd_backward": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp,
                                   _sz, _vp, _vp, _vp]),
+    "tsqr_batch_plan_create": (_i32, [_i32, _vp, _vp, _vp, _vp, _vp, _i32, _vp, _vp]),
+    "tsqr_batch_plan_destroy": (_i32, [_vp]),
+    "tsqr_batch_workspace_bytes": (_i32, [_vp, ctypes.POINTER(_sz)]),
+    "tsqr_batch_plan_launches": (_i32, [_vp, ctypes.POINTER(_i32)]),
+    "tsqr_qr_batched": (_i32, [_vp, _vp, _vp, _vp, _vp, _sz, _vp, _vp]),
+    "tsqr_tune_set": (_i32, [_i32, _i64, _i32]),
+    "tsqr_tune_get": (_i32, [_i32, _i64, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
+    "tsqr_tune_variants": (_i32, [_i32, _i64, _i32, ctypes.POINTER(_i32), ctypes.POINTER(_i32)]),
     "tsqr_plan_levels": (_i32, [_i32, _i64, _i64, _vp, _i32, ctypes.POINTER(_i32),
                                  ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "tsqr_profile_enable": (_i32, [_i32]),

@@ -15,16 +15,11 @@
 #include "tsqr_internal.h"
 
 namespace tsqr {
-namespace {
 
-// ---- optional per-launch timing (benchmarks): HIP event pairs on the launch stream ----------
-enum ProfClass {
-    PC_FACTOR0 = 0, PC_FACTOR_TREE, PC_FINALIZE, PC_APPLY_TREE, PC_APPLY0, PC_REFINE,
-    PC_BWD_GRAM, PC_BWD_SMALL, PC_BWD_GEMM, PC_COUNT
-};
 const char *kProfNames[PC_COUNT] = {"factor_level0", "factor_tree", "finalize_svd",
                                     "apply_tree", "apply_level0", "refine",
                                     "bwd_gram", "bwd_small", "bwd_gemm"};
+
 struct ProfRec { int cls; hipEvent_t a, b; };
 struct Profiler {
     std::mutex mu;
@@ -32,7 +27,20 @@ struct Profiler {
     std::vector<hipEvent_t> pool;
     std::vector<ProfRec> recs;
     size_t next = 0;
-} g_prof;
+};
+
+// text of the most recent HIP failure (per thread), for tsqr_last_error()
+thread_local char g_last_error[512] = "";
+
+void set_last_error(hipError_t e, const char *what, int line)
+{
+    snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in %.300s [line %d]",
+             hipGetErrorString(e), (int)e, what, line);
+}
+
+namespace {
+
+Profiler g_prof;
 
 hipEvent_t prof_event()
 {
@@ -42,37 +50,6 @@ hipEvent_t prof_event()
     g_prof.pool.push_back(e);
     g_prof.next = g_prof.pool.size();
     return e;
-}
-
-struct ProfScope {
-    int cls;
-    hipStream_t st;
-    hipEvent_t a = nullptr;
-    ProfScope(int c, hipStream_t s) : cls(c), st(s)
-    {
-        if (!g_prof.on) return;
-        std::lock_guard<std::mutex> lk(g_prof.mu);
-        a = prof_event();
-        if (a) hipEventRecord(a, st);
-    }
-    ~ProfScope()
-    {
-        if (!a) return;
-        std::lock_guard<std::mutex> lk(g_prof.mu);
-        hipEvent_t b = prof_event();
-        if (!b) return;
-        hipEventRecord(b, st);
-        g_prof.recs.push_back({cls, a, b});
-    }
-};
-
-// text of the most recent HIP failure (per thread), for tsqr_last_error()
-thread_local char g_last_error[512] = "";
-
-void set_last_error(hipError_t e, const char *what, int line)
-{
-    snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in %.300s [api.hip:%d]",
-             hipGetErrorString(e), (int)e, what, line);
 }
 
 enum Op { OP_R = TSQR_OP_R, OP_QR = TSQR_OP_QR, OP_SVD = TSQR_OP_SVD };
@@ -169,14 +146,6 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
 
 inline char *wsp(void *ws, size_t off) { return off ? (char *)ws + off : nullptr; }
 
-#define TSQR_HIP_CHECK(expr)                                                                \
-    do {                                                                                    \
-        hipError_t e_ = (expr);                                                             \
-        if (e_ != hipSuccess) {                                                             \
-            set_last_error(e_, #expr, __LINE__);                                            \
-            return TSQR_ERR_HIP;                                                            \
-        }                                                                                   \
-    } while (0)
 
 // Steps 1-2 (+ finalize): every level's factor launch, then the top.
 tsqr_status run_factor_levels(const Plan &pl, const void *A, int64_t lda, void *ws,
@@ -330,6 +299,27 @@ tsqr_status build_bwd_layout(bool svd, int64_t m, int64_t n, const tsqr_opts *o,
 
 constexpr int kBwdPanel = 256;   // rows per work-group of the backward's tall products
 
+}  // namespace
+
+ProfScope::ProfScope(int c, hipStream_t s) : cls(c), st(s)
+{
+    if (!g_prof.on) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    a = prof_event();
+    if (a) hipEventRecord(a, st);
+}
+
+ProfScope::~ProfScope()
+{
+    if (!a) return;
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    hipEvent_t b = prof_event();
+    if (!b) return;
+    hipEventRecord(b, st);
+    g_prof.recs.push_back({cls, a, b});
+}
+
+namespace {
 }  // namespace
 }  // namespace tsqr
 

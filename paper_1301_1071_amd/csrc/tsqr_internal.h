@@ -14,6 +14,31 @@ constexpr int kMaxLevels = 48;         // recursion depth limit of the in-HBM tr
 constexpr size_t kAlign = 256;         // workspace sub-buffer alignment
 constexpr int kNmaxPad = 128;          // column capacity of per-column LDS arrays (>= TSQR_NMAX)
 
+// ---- optional per-launch timing (benchmarks): HIP event pairs on the launch stream (api.hip)
+enum ProfClass {
+    PC_FACTOR0 = 0, PC_FACTOR_TREE, PC_FINALIZE, PC_APPLY_TREE, PC_APPLY0, PC_REFINE,
+    PC_BWD_GRAM, PC_BWD_SMALL, PC_BWD_GEMM, PC_COUNT
+};
+extern const char *kProfNames[PC_COUNT];
+struct ProfScope {
+    int cls;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(int c, hipStream_t s);
+    ~ProfScope();
+};
+
+// Record the text of a failed HIP call for tsqr_last_error().
+void set_last_error(hipError_t e, const char *what, int line);
+#define TSQR_HIP_CHECK(expr)                                                                \
+    do {                                                                                    \
+        hipError_t e_ = (expr);                                                             \
+        if (e_ != hipSuccess) {                                                             \
+            ::tsqr::set_last_error(e_, #expr, __LINE__);                                    \
+            return TSQR_ERR_HIP;                                                            \
+        }                                                                                   \
+    } while (0)
+
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 

@@ -231,3 +231,101 @@ def qr_autograd(A: torch.Tensor):
 def svd_autograd(A: torch.Tensor):
     """Differentiable thin SVD by direct TSQR (FP64)."""
     return SVDFunction.apply(A)
+
+
+# ----------------------------------------------------------------------------- batched form
+_DTYPES = {torch.float64: 0, torch.float32: 1}
+
+
+class BatchPlan:
+    """A batched-QR plan for fixed shapes (tsqr_batch_plan_create): the per-matrix trees, the
+    workspace size and the device task tables.  `run` only enqueues kernels, so it can be
+    captured in a CUDA/HIP graph."""
+
+    def __init__(self, shapes, dtype=torch.float64, lda=None, ldq=None, ldr=None,
+                 panel_rows: int = 0, device=None):
+        from .tuning import ensure_loaded
+        ensure_loaded()
+        self.shapes = [(int(m), int(n)) for m, n in shapes]
+        self.dtype = dtype
+        self.device = torch.device(device) if device is not None else torch.device("cuda", torch.cuda.current_device())
+        b = len(self.shapes)
+        arr = lambda xs: (ctypes.c_int64 * b)(*xs)
+        ms = arr([m for m, _ in self.shapes])
+        ns = arr([n for _, n in self.shapes])
+        self._ld = (arr(lda or [n for _, n in self.shapes]), arr(ldq or [n for _, n in self.shapes]),
+                    arr(ldr or [n for _, n in self.shapes]))
+        o = make_opts("fp32" if dtype == torch.float32 else "fp64", panel_rows)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().tsqr_batch_plan_create(b, ms, ns, *self._ld, _DTYPES[dtype], ctypes.byref(o),
+                                               ctypes.byref(h)), "tsqr_batch_plan_create")
+        self._h = h
+        nb = ctypes.c_size_t(0)
+        check(lib().tsqr_batch_workspace_bytes(h, ctypes.byref(nb)), "tsqr_batch_workspace_bytes")
+        self.workspace_bytes = int(nb.value)
+        nl = ctypes.c_int32(0)
+        check(lib().tsqr_batch_plan_launches(h, ctypes.byref(nl)), "tsqr_batch_plan_launches")
+        self.launches = int(nl.value)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().tsqr_batch_plan_destroy(h)
+            self._h = None
+
+    @staticmethod
+    def pointers(tensors, device):
+        return torch.tensor([t.data_ptr() for t in tensors], dtype=torch.int64, device=device)
+
+    def run(self, ptrs_a: torch.Tensor, ptrs_q: torch.Tensor, ptrs_r: torch.Tensor,
+            ws: torch.Tensor, info: torch.Tensor) -> None:
+        """Enqueue the batched factorization on the current stream (no checks of d_info)."""
+        check(lib().tsqr_qr_batched(self._h, _p(ptrs_a), _p(ptrs_q), _p(ptrs_r), _p(ws), ws.numel(),
+                                    _p(info), _stream(ws.device)), "tsqr_qr_batched")
+
+
+def qr_batched(As, panel_rows: int = 0, check_info: bool = True):
+    """Thin QR of every matrix in the list `As` (2-D GPU tensors, one dtype, n <= 64, row-major
+    with unit column stride) in one batched launch sequence; returns a list of (Q, R)."""
+    if not As:
+        return []
+    dtype = As[0].dtype
+    dev = As[0].device
+    for A in As:
+        _require_gpu_matrix(A, (torch.float64, torch.float32))
+        if A.dtype != dtype or A.device != dev:
+            raise TypeError("all matrices of a batch must share dtype and device")
+    shapes = [tuple(A.shape) for A in As]
+    plan = BatchPlan(shapes, dtype, lda=[A.stride(0) for A in As], panel_rows=panel_rows,
+                     device=dev)
+    Qs = [torch.empty(s, dtype=dtype, device=dev) for s in shapes]
+    Rs = [torch.empty((s[1], s[1]), dtype=dtype, device=dev) for s in shapes]
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    info = torch.zeros(len(As), dtype=torch.int32, device=dev)
+    plan.run(BatchPlan.pointers(As, dev), BatchPlan.pointers(Qs, dev), BatchPlan.pointers(Rs, dev),
+             ws, info)
+    if check_info:
+        bad = torch.nonzero(info).flatten().tolist()
+        if bad:
+            raise torch.linalg.LinAlgError("tsqr_qr_batched: info != 0 for matrices %s (values %s)"
+                                           % (bad[:8], info[bad[:8]].tolist()))
+    return list(zip(Qs, Rs))
+
+
+def tune_set(dtype, n: int, variant: int) -> None:
+    check(lib().tsqr_tune_set(_DTYPES[dtype], n, variant), "tsqr_tune_set")
+
+
+def tune_get(dtype, n: int):
+    v, b = ctypes.c_int32(0), ctypes.c_int32(0)
+    check(lib().tsqr_tune_get(_DTYPES[dtype], n, ctypes.byref(v), ctypes.byref(b)), "tsqr_tune_get")
+    return int(v.value), int(b.value)
+
+
+def tune_variants(dtype, n: int):
+    """Panel heights of the register-panel variants for width n (0 = unusable variant)."""
+    buf = (ctypes.c_int32 * 8)()
+    c = ctypes.c_int32(0)
+    check(lib().tsqr_tune_variants(_DTYPES[dtype], n, 8, buf, ctypes.byref(c)), "tsqr_tune_variants")
+    return [int(buf[i]) for i in range(c.value)]

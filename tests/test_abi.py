@@ -158,3 +158,42 @@ def test_plan_levels_shape():
         assert rows_next == panels * 50          # the stacked R of the level below
         assert rows_next < rows
     assert lv[-1][1] == lv[-1][0]                # the top is one panel
+
+
+def test_batched_plan_validation_without_gpu():
+    """Shape and option errors of tsqr_batch_plan_create return before any device call."""
+    L = lib()
+    b = 3
+    arr = lambda xs: (ctypes.c_int64 * b)(*xs)
+    h = ctypes.c_void_p()
+    ms, ns = arr([100, 200, 300]), arr([4, 8, 16])
+    good = arr([64, 64, 64])
+    assert L.tsqr_batch_plan_create(0, ms, ns, good, good, good, 0, None, ctypes.byref(h)) == 1
+    assert L.tsqr_batch_plan_create(b, ms, ns, good, good, good, 5, None, ctypes.byref(h)) == 1
+    wide = arr([70, 70, 70])
+    assert L.tsqr_batch_plan_create(b, ms, arr([4, 8, 65]), wide, wide, wide, 0, None,
+                                    ctypes.byref(h)) == 2                        # n > 64
+    assert L.tsqr_batch_plan_create(b, arr([100, 5, 300]), ns, good, good, good, 0, None,
+                                    ctypes.byref(h)) == 2                        # m < n
+    assert L.tsqr_batch_plan_create(b, ms, ns, arr([4, 7, 16]), good, good, 0, None,
+                                    ctypes.byref(h)) == 1                        # lda < n
+    o = make_opts("fp32")
+    assert L.tsqr_batch_plan_create(b, ms, ns, good, good, good, 0, ctypes.byref(o),
+                                    ctypes.byref(h)) == 4                        # precision != dtype
+    assert L.tsqr_qr_batched(None, FAKE, FAKE, FAKE, FAKE, 1 << 20, FAKE, None) == 1
+    assert L.tsqr_batch_plan_destroy(None) == 1
+
+
+def test_tune_table_queries():
+    L = lib()
+    buf = (ctypes.c_int32 * 4)()
+    c = ctypes.c_int32()
+    assert L.tsqr_tune_variants(0, 4, 4, buf, ctypes.byref(c)) == 0 and c.value == 3
+    assert buf[0] > buf[1] > 0
+    assert L.tsqr_tune_variants(0, 64, 4, buf, ctypes.byref(c)) == 0
+    assert buf[0] >= 3 * 64 and buf[1] == 0 and buf[2] == 0    # half height too short at n = 64
+    assert L.tsqr_tune_set(0, 64, 1) == 1                        # unusable variant rejected
+    assert L.tsqr_tune_set(0, 65, 0) == 1
+    v, rows = ctypes.c_int32(), ctypes.c_int32()
+    assert L.tsqr_tune_get(1, 16, ctypes.byref(v), ctypes.byref(rows)) == 0
+    assert rows.value > 0
