@@ -38,7 +38,8 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="svd-c50",
-                    choices=["svd-c50", "qr-small", "mixed-c25", "grad-c100"])
+                    choices=["svd-c50", "qr-small", "mixed-c25", "grad-c100", "batch512",
+                             "batch512-f32"])
     ap.add_argument("--rows", type=int, default=0, help="override m (same recipe and seed)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-accuracy", action="store_true")
@@ -69,6 +70,8 @@ def main():
 
     dev = torch.device("cuda:0")
     name = args.workload
+    if name.startswith("batch512"):
+        return bench_batched(args, torch.float32 if name.endswith("f32") else torch.float64)
     cfg = workloads.CONFIGS[name]
     m = args.rows or cfg["m"]
     n = cfg["n"]
@@ -154,6 +157,8 @@ def main():
     roof = roofline(dom, dom_ms_launch, m, n, plan_op, precision, _lib)
     roof["kernel"] = dom
     roof["ms_per_launch"] = dom_ms_launch
+    if args.rows == 0 and precision == "fp64":
+        roof["traffic"] = MEASURED_TRAFFIC.get((name, dom))
 
     line = {
         "metric": METRIC,
@@ -194,6 +199,140 @@ def main():
         line["cpu_baseline"] = cpu_baseline(name, A_h, n, args.cpu_sample_rows)
 
     print(json.dumps(line), flush=True)
+
+
+def bench_batched(args, dtype):
+    """batch512: 512 matrices, m ~ U{2,000..200,000}, n ~ U{4,8,16,32,64}, N(0,1) (FP32: the
+    rounding of the same draws); a step is one tsqr_qr_batched call over the whole batch."""
+    import torch
+    import paper_1301_1071_amd as tsqr
+    from paper_1301_1071_amd import _lib
+    import workloads
+
+    dev = torch.device("cuda:0")
+    f32 = dtype == torch.float32
+    es = 4 if f32 else 8
+    shapes = workloads.batch_shapes()
+    mats = workloads.batch_matrices(shapes, dtype=np.float32 if f32 else np.float64)
+    As = [torch.from_numpy(A).to(dev) for A in mats]
+    plan = tsqr.BatchPlan(shapes, dtype)
+    Qs = [torch.empty_like(A) for A in As]
+    Rs = [torch.empty((n, n), dtype=dtype, device=dev) for _, n in shapes]
+    ws = torch.empty(plan.workspace_bytes, dtype=torch.uint8, device=dev)
+    info = torch.zeros(len(As), dtype=torch.int32, device=dev)
+    P = tsqr.BatchPlan.pointers
+    pa, pq, pr = P(As, dev), P(Qs, dev), P(Rs, dev)
+
+    def step():
+        plan.run(pa, pq, pr, ws, info)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    _lib.profile_collect()
+    _lib.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _lib.profile_enable(False)
+    prof = _lib.profile_collect()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    # the same call captured once in a graph and replayed
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        step()
+    g.replay()
+    torch.cuda.synchronize()
+    tg0 = time.perf_counter()
+    for _ in range(args.steps):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - tg0) * 1e3 / args.steps
+
+    sum_mn = float(sum(m * n for m, n in shapes))
+    alg_bytes = 2.0 * es * sum_mn                    # read every A_i, write every Q_i
+    value = alg_bytes / (ms_step * 1e-3) / 1e9
+    kernels = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps}
+               for k, v in prof.items() if v[1] > 0}
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    dom_ms_launch = prof[dom][0] / prof[dom][1]
+    launches = prof[dom][1] / args.steps
+    if dom == "factor_level0":
+        flops = sum(level0_flops(m, n, tsqr.tune_get(dtype, n)[1], form_q=True) for m, n in shapes)
+        byts = 2.0 * es * sum_mn
+    elif dom == "apply_level0":
+        flops, byts = sum(2.0 * m * n * n for m, n in shapes), 2.0 * es * sum_mn
+    else:
+        flops, byts = 0.0, 2.0 * es * sum_mn
+    flops /= launches                                # per launch (one launch per width)
+    byts /= launches
+    peak_t = FP32_PEAK_TFLOPS if f32 else FP64_PEAK_TFLOPS
+    sec = dom_ms_launch * 1e-3
+    if flops / byts > peak_t * 1e12 / (HBM_PEAK_GBS * 1e9):
+        a = flops / sec / 1e12
+        roof = {"bound": "alu", "achieved": a, "peak": peak_t, "unit": "TFLOP/s",
+                "frac": a / peak_t, "traffic": None}
+    else:
+        a = byts / sec / 1e9
+        roof = {"bound": "hbm", "achieved": a, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": a / HBM_PEAK_GBS, "traffic": None}
+    roof.update({"kernel": dom, "ms_per_launch": dom_ms_launch})
+    per_n = {}
+    for (m, n) in shapes:
+        per_n.setdefault(n, [0, 0])
+        per_n[n][0] += 1
+        per_n[n][1] += m
+    line = {
+        "metric": METRIC, "value": value, "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if f32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": "batch512" + ("-f32" if f32 else ""), "matrices": len(shapes),
+                   "sum_rows": int(sum(m for m, _ in shapes)),
+                   "per_width": {str(k): {"count": v[0], "rows": v[1]} for k, v in sorted(per_n.items())},
+                   "seed": workloads.SEEDS["batch512"], "algorithmic_bytes": alg_bytes,
+                   "launches_per_call": plan.launches},
+        "hbm_frac": value / HBM_PEAK_GBS,
+        "rows_per_s": sum(m for m, _ in shapes) / (ms_step * 1e-3),
+        "graph_ms_per_step": graph_ms,
+        "roofline": roof,
+        "kernels": kernels,
+    }
+    if not args.no_accuracy:
+        import oracle
+        worst = {"orth": 0.0, "backward": 0.0}
+        for k in range(0, len(mats), 64):           # every 64th matrix, full metrics
+            A = mats[k].astype(np.float64)
+            Q = Qs[k].cpu().numpy().astype(np.float64)
+            R = Rs[k].cpu().numpy().astype(np.float64)
+            worst["orth"] = max(worst["orth"], oracle.metric_orth(Q))
+            worst["backward"] = max(worst["backward"], oracle.metric_backward(A, Q, R))
+        line["accuracy"] = worst
+    if not args.no_cpu_baseline:
+        import oracle
+        t0 = time.perf_counter()
+        done, byts = 0, 0.0
+        while time.perf_counter() - t0 < 10.0 and done < len(mats):
+            A = mats[done].astype(np.float64)
+            oracle.tsqr(A, block_rows=1000)
+            byts += 2.0 * es * A.shape[0] * A.shape[1]
+            done += 1
+        dt = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": byts / dt / 1e9, "unit": "GB/s",
+                                "cores": oracle.max_threads(0), "kind": "oracle",
+                                "sample": "first %d of %d matrices, oracle blocks of 1,000 rows, "
+                                          "%.1f s" % (done, len(mats), dt)}
+    print(json.dumps(line), flush=True)
+
+
+# HBM bytes per launch of a kernel class, measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs
+# (scaled by the copy calibration) for the kernels as they are now; the summaries with the
+# commands are in profiles/.  Keyed by (workload, kernel class).
+MEASURED_TRAFFIC = {
+    ("svd-c50", "factor_level0"): 3.617e9,      # profiles/factor_reg_svd-c50.md
+}
 
 
 def roofline(dom, ms_launch, m, n, plan_op, precision, _lib):
