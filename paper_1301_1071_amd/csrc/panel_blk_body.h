@@ -1,0 +1,348 @@
+// Blocked Householder panel factorization on the matrix cores (FP64, n <= 64): the device body
+// shared by the single-matrix and batched launches.
+//
+// Step 1 of direct TSQR (Sec. III-B) for one row panel of B = NW * RT * 16 rows per work-group.
+// The panel lives in registers in the accumulator layout of v_mfma_f64_16x16x4: it is cut into
+// 16 x 16 tiles; wave w owns row tiles w*RT .. w*RT+RT-1 of every column tile, and lane l holds
+// element (l/16 + 4i, l%16) of a tile in value i.  Columns are factored in blocks of 16 (one
+// column tile):
+//   * inside a block, Householder column k (Sec. III-A) is one barrier-separated step: the pivot
+//     column is broadcast within each 16-lane row group, the dot products with the block's 16
+//     columns are reduced over the lanes, the waves (through LDS) and the rows, and the block's
+//     columns get the rank-1 update;
+//   * the block's reflectors are then gathered as V (unit lower trapezoidal) with the compact
+//     WY factor T = (striu(V^T V) + diag(1/tau))^{-1} (upper triangular), and the trailing column
+//     tiles receive A <- (I - V T^T V^T) A through two products on the matrix cores:
+//     W = V^T A (the accumulator layout of V is directly the A operand of V^T) and A -= V (T^T W)
+//     (V re-laid out through LDS as the A operand);
+//   * the explicit Q1 = H_1 ... H_n [I; 0] is formed in place afterwards, block by block from
+//     the last, with the same two products and T in place of T^T, so step 3 stays a plain GEMM.
+//
+// Householder convention (as in the other panel kernels): beta = -sign(alpha) sqrt(alpha^2 + s2),
+// tau = (beta - alpha)/beta, v = [1; x/(alpha - beta)], tau = 0 when the column below the
+// diagonal is already zero.  The x below the diagonal is kept unscaled until V is gathered.
+#pragma once
+
+#include <type_traits>
+
+#include "tsqr_internal.h"
+
+namespace tsqr {
+namespace blkpanel {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ d4_t mfma4(double a, double b, d4_t c)
+{
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// value of lane (this lane's 16-lane row group, column kk)
+__device__ __forceinline__ double bcast16(double v, int kk)
+{
+    const int lane = threadIdx.x & 63;
+    return __shfl(v, (lane & 48) | kk, 64);
+}
+
+__device__ __forceinline__ double rcp_refined(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+
+template <int I, int N, typename F> __device__ __forceinline__ void static_for(F &&f)
+{
+    if constexpr (I < N) {
+        f(std::integral_constant<int, I>{});
+        static_for<I + 1, N>(f);
+    }
+}
+
+template <int NCT, int RT, int NW> struct BlkCfg {
+    static constexpr int B = NW * RT * 16;
+    static constexpr int NCOL = NCT * 16;
+};
+
+// LDS of one work-group
+template <int NCT, int RT, int NW> struct BlkSmem {
+    double part[2][NW][16];          // per-step partial dots of the block's columns
+    double rowk[2][16];              // pivot row k restricted to the block
+    double tau[NCT * 16], u[NCT * 16], beta[NCT * 16];
+    union {
+        double red[NW][NCT][256];    // per-wave partial products (G, W) before the wave sum
+        double vt[NW][16][17];       // one row tile of V per wave, row-major (A operand of V Y)
+    };
+    double wsum[NCT][256];           // summed products: slot kt = G = V^T V, slot t = W of tile t
+    double tstore[NCT][16][17];      // T of every block (kept for the Q1 formation)
+    double ybuf[16][NCT * 16 + 1];   // Y = T^T W (or T W) for the trailing tiles
+};
+
+template <int NCT, int RT, int NW>
+__device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const double *__restrict__ X,
+                                                 int64_t ldx, double *__restrict__ q1,
+                                                 double *__restrict__ S, int64_t p)
+{
+    constexpr int B = NW * RT * 16;
+    constexpr int NT = NW * 64;
+    __shared__ BlkSmem<NCT, RT, NW> sm;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int lc = lane & 15, lr = lane >> 4;
+    const int64_t prow0 = p * (int64_t)B;
+    const int nrow = (int)min((int64_t)B, rows - prow0);
+    auto row_of = [&](int rt, int i) { return 16 * (w * RT + rt) + lr + 4 * i; };
+
+    // ---- load the panel (zero rows past the end and columns past n) -------------------------
+    d4_t P[RT][NCT];
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = row_of(rt, i), c = 16 * ct + lc;
+                P[rt][ct][i] = (r < nrow && c < n) ? X[(prow0 + r) * ldx + c] : 0.0;
+            }
+
+    // V of block KT from the stored x's: unit diagonal, zero above, x / (alpha - beta) below;
+    // zero for a skipped reflector (tau = 0) or a padding column
+    auto gather_v = [&](auto KT, double (&V)[RT][4]) {
+        constexpr int kt = decltype(KT)::value;
+        const int c = 16 * kt + lc;
+        const double tc = (c < n) ? sm.tau[c] : 0.0;
+        const double inv = (tc != 0.0) ? rcp_refined(sm.u[c]) : 0.0;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = row_of(rt, i);
+                double v = 0.0;
+                if (tc != 0.0) v = (r > c) ? P[rt][kt][i] * inv : ((r == c) ? 1.0 : 0.0);
+                V[rt][i] = v;
+            }
+    };
+
+    // W_t = V^T A[:, tile t] for tiles t >= T0 into wsum[t], and with WITH_G also G = V^T V into
+    // wsum[KT] (then T0 > KT); summed over the waves in a fixed order.  Ends with a barrier.
+    auto block_products = [&](auto KT, auto T0, auto WITH_G, const double (&V)[RT][4]) {
+        constexpr int kt = decltype(KT)::value, t0 = decltype(T0)::value;
+        constexpr bool with_g = decltype(WITH_G)::value;
+        d4_t acc[NCT];
+#pragma unroll
+        for (int t = 0; t < NCT; ++t) acc[t] = d4_t{0, 0, 0, 0};
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                if constexpr (with_g) acc[kt] = mfma4(V[rt][i], V[rt][i], acc[kt]);
+#pragma unroll
+                for (int t = t0; t < NCT; ++t) acc[t] = mfma4(V[rt][i], P[rt][t][i], acc[t]);
+            }
+#pragma unroll
+        for (int t = 0; t < NCT; ++t)
+            if (t >= t0 || (with_g && t == kt))
+#pragma unroll
+                for (int i = 0; i < 4; ++i) sm.red[w][t][(lr + 4 * i) * 16 + lc] = acc[t][i];
+        __syncthreads();
+        for (int e = tid; e < NCT * 256; e += NT) {
+            const int t = e >> 8;
+            if (!(t >= t0 || (with_g && t == kt))) continue;
+            double s = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) s += sm.red[ww][t][e & 255];
+            sm.wsum[t][e & 255] = s;
+        }
+        __syncthreads();
+    };
+
+    // T of block KT from G = wsum[KT]: T = (striu(G) + diag(1/tau))^{-1}; thread j solves
+    // column j by back substitution (a skipped reflector gets a unit diagonal).  Ends with a
+    // barrier.
+    auto block_t = [&](auto KT) {
+        constexpr int kt = decltype(KT)::value;
+        if (tid < 16) {
+            const int j = tid;
+            for (int i = 15; i > j; --i) sm.tstore[kt][i][j] = 0.0;
+            for (int i = j; i >= 0; --i) {
+                const int ci = 16 * kt + i;
+                const double ti = (ci < n) ? sm.tau[ci] : 0.0;
+                double acc = (i == j) ? 1.0 : 0.0;
+                for (int l = i + 1; l <= j; ++l)
+                    acc = fma(-sm.wsum[kt][i * 16 + l], sm.tstore[kt][l][j], acc);
+                sm.tstore[kt][i][j] = (ti != 0.0) ? acc * ti : acc;
+            }
+        }
+        __syncthreads();
+    };
+
+    // A[:, tiles t >= T0] -= V * Y[:, tiles], Y in sm.ybuf; V re-laid out row tile by row tile
+    // through this wave's sm.vt as the row-major A operand
+    auto block_update = [&](auto T0, const double (&V)[RT][4]) {
+        constexpr int t0 = decltype(T0)::value;
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sm.vt[w][lr + 4 * i][lc] = V[rt][i];
+            // (the wave reads back what its own lanes wrote: LDS operations of a wave are ordered)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double a = sm.vt[w][lc][4 * q + lr];
+#pragma unroll
+                for (int t = t0; t < NCT; ++t)
+                    P[rt][t] = mfma4(a, -sm.ybuf[4 * q + lr][16 * t + lc], P[rt][t]);
+            }
+        }
+    };
+
+    // ---- factorization, block by block ---------------------------------------------------
+    int nstep = 0;
+    static_for<0, NCT>([&](auto KT) {
+        constexpr int kt = decltype(KT)::value;
+        if (16 * kt >= n) return;
+        const int kend = min(16 * kt + 16, n);
+        for (int k = 16 * kt; k < kend; ++k, ++nstep) {
+            const int kk = k - 16 * kt;
+            const int par = nstep & 1;
+            // publish row k of the block (after the previous step's update)
+            {
+                const int rtile = k >> 4;                 // global row tile of row k
+                if (rtile / RT == w && lr == (k & 3)) {
+                    const int rt = rtile - w * RT, ik = (k & 15) >> 2;
+                    double v = 0.0;
+#pragma unroll
+                    for (int r2 = 0; r2 < RT; ++r2)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i)
+                            if (r2 == rt && i == ik) v = P[r2][kt][i];
+                    sm.rowk[par][lc] = v;
+                }
+            }
+            // pivot column x (rows > k) and the partial dots with the block's columns
+            double xm[RT][4];
+            double d = 0.0;
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const double xv = bcast16(P[rt][kt][i], kk);
+                    xm[rt][i] = (row_of(rt, i) > k) ? xv : 0.0;
+                    d = fma(xm[rt][i], P[rt][kt][i], d);
+                }
+            d += __shfl_xor(d, 16, 64);
+            d += __shfl_xor(d, 32, 64);
+            if (lr == 0) sm.part[par][w][lc] = d;
+            __syncthreads();
+            double s2 = 0.0, pc = 0.0;
+#pragma unroll
+            for (int ww = 0; ww < NW; ++ww) {
+                s2 += sm.part[par][ww][kk];
+                pc += sm.part[par][ww][lc];
+            }
+            const double alpha = sm.rowk[par][kk];
+            double tau = 0.0, u = 0.0, beta = alpha;
+            if (s2 != 0.0) {
+                const double nrm = sqrt(alpha * alpha + s2);
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                tau = 1.0 - alpha * rcp_refined(beta);
+                u = alpha - beta;
+            }
+            if (tid == 0) { sm.tau[k] = tau; sm.u[k] = u; sm.beta[k] = beta; }
+            double coef = 0.0;
+            if (tau != 0.0 && lc > kk && 16 * kt + lc < n) {
+                const double inv = rcp_refined(u);
+                coef = tau * (sm.rowk[par][lc] + inv * pc) * inv;
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = row_of(rt, i);
+                    const double x = (r == k) ? u : xm[rt][i];
+                    P[rt][kt][i] = fma(-coef, x, P[rt][kt][i]);
+                }
+        }
+        __syncthreads();      // tau, u of the block visible to every wave
+        if constexpr (kt + 1 < NCT) {
+            if (16 * (kt + 1) < n) {
+                double V[RT][4];
+                gather_v(KT, V);
+                block_products(KT, std::integral_constant<int, kt + 1>{}, std::true_type{}, V);
+                block_t(KT);
+                // Y = T^T W for the trailing tiles
+                for (int e = tid; e < 16 * NCT * 16; e += NT) {
+                    const int m = e / (16 * NCT), c = e - m * (16 * NCT);
+                    if ((c >> 4) <= kt) continue;
+                    double acc = 0.0;
+                    for (int j = 0; j <= m; ++j)
+                        acc = fma(sm.tstore[kt][j][m], sm.wsum[c >> 4][j * 16 + (c & 15)], acc);
+                    sm.ybuf[m][c] = acc;
+                }
+                __syncthreads();
+                block_update(std::integral_constant<int, kt + 1>{}, V);
+            }
+        }
+    });
+    __syncthreads();
+
+    // ---- R_p: rows 0..n-1, strict upper part from the registers, diagonal = beta -----------
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = row_of(rt, i), c = 16 * ct + lc;
+                if (r < n && c < n)
+                    S[(p * n + r) * n + c] = (c > r) ? P[rt][ct][i] : ((c == r) ? sm.beta[r] : 0.0);
+            }
+    if (q1 == nullptr) return;
+
+    // ---- explicit Q1 = H_1 ... H_n [I; 0], in place, block by block from the last -----------
+    const int nblk = (n + 15) >> 4;
+    static_for<0, NCT>([&](auto I) {
+        constexpr int kt = NCT - 1 - decltype(I)::value;
+        if (kt >= nblk) return;
+        using KT = std::integral_constant<int, kt>;
+        double V[RT][4];
+        gather_v(KT{}, V);
+        if (kt == nblk - 1) {
+            // the last block's T (its trailing step did not run)
+            block_products(KT{}, std::integral_constant<int, NCT>{}, std::true_type{}, V);
+            block_t(KT{});
+        }
+        // the block's own columns are still identity columns of [I; 0]
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                P[rt][kt][i] = (row_of(rt, i) == 16 * kt + lc) ? 1.0 : 0.0;
+        block_products(KT{}, KT{}, std::false_type{}, V);
+        // Y = T W for tiles >= kt
+        for (int e = tid; e < 16 * NCT * 16; e += NT) {
+            const int m = e / (16 * NCT), c = e - m * (16 * NCT);
+            if ((c >> 4) < kt) continue;
+            double acc = 0.0;
+            for (int j = m; j < 16; ++j)
+                acc = fma(sm.tstore[kt][m][j], sm.wsum[c >> 4][j * 16 + (c & 15)], acc);
+            sm.ybuf[m][c] = acc;
+        }
+        __syncthreads();
+        block_update(KT{}, V);
+        __syncthreads();
+    });
+#pragma unroll
+    for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = row_of(rt, i), c = 16 * ct + lc;
+                if (r < nrow && c < n) q1[(prow0 + r) * n + c] = P[rt][ct][i];
+            }
+}
+
+}  // namespace blkpanel
+}  // namespace tsqr

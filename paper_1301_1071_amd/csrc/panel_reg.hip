@@ -1,5 +1,6 @@
 // Register-resident panel kernels of the single-matrix path: the panel factorization (device
 // body in panel_reg_body.h) and the LDS-staged vector apply.
+#include "panel_blk_body.h"
 #include "panel_reg_body.h"
 
 
@@ -14,6 +15,51 @@ k_factor_reg(int64_t rows, int n, const Tin *__restrict__ X, int64_t ldx, T *__r
              double *__restrict__ S)
 {
     factor_reg_panel<Tin, T, NC, CPL, RW, NW>(rows, n, X, ldx, q1, S, blockIdx.x);
+}
+
+template <int NCT, int RT, int NW>
+__global__ void __launch_bounds__(NW * 64, 2)
+k_factor_blk(int64_t rows, int n, const double *__restrict__ X, int64_t ldx,
+             double *__restrict__ q1, double *__restrict__ S)
+{
+    blkpanel::factor_blk_panel<NCT, RT, NW>(rows, n, X, ldx, q1, S, blockIdx.x);
+}
+
+// Panel shapes of the blocked FP64 kernel (4 waves, two work-groups per CU without spills):
+// 256 rows for n > 32, 384 for n <= 32, 512 for n <= 16.
+template <int NCT> struct BlkShape {
+    static constexpr int NW = 4;
+    static constexpr int RT = (NCT >= 3) ? 4 : (NCT == 2 ? 6 : 8);
+    static constexpr int B = NW * RT * 16;
+};
+
+template <int NCT>
+hipError_t factor_blk_launch(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
+                             double *S, hipStream_t st)
+{
+    using C = BlkShape<NCT>;
+    const int64_t panels = ceil_div(rows, C::B);
+    hipLaunchKernelGGL((k_factor_blk<NCT, C::RT, C::NW>), dim3((unsigned)panels),
+                       dim3(C::NW * 64), 0, st, rows, (int)n, (const double *)X, ldx,
+                       (double *)q1, S);
+    return hipGetLastError();
+}
+
+hipError_t factor_blk_dispatch(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
+                               double *S, hipStream_t st)
+{
+    if (n <= 16) return factor_blk_launch<1>(rows, n, X, ldx, q1, S, st);
+    if (n <= 32) return factor_blk_launch<2>(rows, n, X, ldx, q1, S, st);
+    if (n <= 48) return factor_blk_launch<3>(rows, n, X, ldx, q1, S, st);
+    return factor_blk_launch<4>(rows, n, X, ldx, q1, S, st);
+}
+
+int blk_panel_rows(int64_t n)
+{
+    if (n <= 16) return BlkShape<1>::B;
+    if (n <= 32) return BlkShape<2>::B;
+    if (n <= 48) return BlkShape<3>::B;
+    return BlkShape<4>::B;
 }
 
 // out rows of panel p = Q1_p (b x n) * W_p (n x k).  Q1 rows are staged through LDS in chunks
@@ -160,6 +206,7 @@ hipError_t apply_staged_dispatch(int64_t rows, int64_t n, int b, const void *q1,
 
 int reg_panel_rows(int64_t n, int dtype)
 {
+    if (dtype == F64 && n <= 64) return blk_panel_rows(n);
     return reg_panel_rows_variant(n, dtype, 0);
 }
 
@@ -167,6 +214,7 @@ hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, c
                              int64_t ldx, void *q1, double *S, hipStream_t st)
 {
     if (dtype == F64) {
+        if (in_dtype == F64 && n <= 64) return factor_blk_dispatch(rows, n, X, ldx, q1, S, st);
         if (in_dtype == F64) return factor_reg_dispatch<double, double>(rows, n, X, ldx, q1, S, st);
         return factor_reg_dispatch<float, double>(rows, n, X, ldx, q1, S, st);
     }
