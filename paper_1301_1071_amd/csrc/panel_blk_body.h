@@ -11,7 +11,7 @@
 //     columns are reduced over the lanes, the waves (through LDS) and the rows, and the block's
 //     columns get the rank-1 update;
 //   * the block's reflectors are then gathered as V (unit lower trapezoidal) with the compact
-//     WY factor T = (striu(V^T V) + diag(1/tau))^{-1} (upper triangular), and the trailing column
+//     WY factor T (upper triangular, from V^T V by the column recurrence), and the trailing column
 //     tiles receive A <- (I - V T^T V^T) A through two products on the matrix cores:
 //     W = V^T A (the accumulator layout of V is directly the A operand of V^T) and A -= V (T^T W)
 //     (V re-laid out through LDS as the A operand);
@@ -37,11 +37,27 @@ __device__ __forceinline__ d4_t mfma4(double a, double b, d4_t c)
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// value of lane (this lane's 16-lane row group, column kk)
-__device__ __forceinline__ double bcast16(double v, int kk)
+// value of lane KK of this lane's 16-lane row (DPP row_newbcast)
+template <int KK> __device__ __forceinline__ double bcast16(double v)
 {
-    const int lane = threadIdx.x & 63;
-    return __shfl(v, (lane & 48) | kk, 64);
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + KK, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + KK, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// v[l] + v[l ^ 16] and v[l] + v[l ^ 32] through the gfx950 lane-swap instructions (the two
+// partners end up in the two outputs, so each pair of lanes forms the same sum)
+__device__ __forceinline__ double sum_xor16(double v)
+{
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double sum_xor32(double v)
+{
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
 }
 
 __device__ __forceinline__ double rcp_refined(double x)
@@ -93,7 +109,9 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
     const int lc = lane & 15, lr = lane >> 4;
     const int64_t prow0 = p * (int64_t)B;
     const int nrow = (int)min((int64_t)B, rows - prow0);
-    auto row_of = [&](int rt, int i) { return 16 * (w * RT + rt) + lr + 4 * i; };
+    // row tiles are dealt out to the waves in turn (tile g belongs to wave g % NW), so the
+    // finished top rows and the pivot tile of every block are spread over the waves
+    auto row_of = [&](int rt, int i) { return 16 * (rt * NW + w) + lr + 4 * i; };
 
     // ---- load the panel (zero rows past the end and columns past n) -------------------------
     d4_t P[RT][NCT];
@@ -158,22 +176,44 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         __syncthreads();
     };
 
-    // T of block KT from G = wsum[KT]: T = (striu(G) + diag(1/tau))^{-1}; thread j solves
-    // column j by back substitution (a skipped reflector gets a unit diagonal).  Ends with a
-    // barrier.
+    // T of block KT (Q_blk = H_1 ... H_16 = I - V T V^T) from G = wsum[KT] = V^T V by the
+    // column recurrence T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], T[j][j] = tau_j: lane i of wave
+    // 0 computes row i of T, which needs only entries of its own row (read back from LDS in
+    // program order), so no barrier is needed inside.  Ends with a barrier.
     auto block_t = [&](auto KT) {
         constexpr int kt = decltype(KT)::value;
-        if (tid < 16) {
-            const int j = tid;
-            for (int i = 15; i > j; --i) sm.tstore[kt][i][j] = 0.0;
-            for (int i = j; i >= 0; --i) {
-                const int ci = 16 * kt + i;
-                const double ti = (ci < n) ? sm.tau[ci] : 0.0;
-                double acc = (i == j) ? 1.0 : 0.0;
-                for (int l = i + 1; l <= j; ++l)
-                    acc = fma(-sm.wsum[kt][i * 16 + l], sm.tstore[kt][l][j], acc);
-                sm.tstore[kt][i][j] = (ti != 0.0) ? acc * ti : acc;
+        if (w == 0 && lane < 16) {
+            const int i = lane;
+            double *trow = sm.tstore[kt][i];
+            for (int j = 0; j < 16; ++j) {
+                const int cj = 16 * kt + j;
+                const double tj = (cj < n) ? sm.tau[cj] : 0.0;
+                double s0 = 0.0, s1 = 0.0;
+                for (int l = i; l < j; l += 2) {
+                    s0 = fma(trow[l], sm.wsum[kt][l * 16 + j], s0);
+                    if (l + 1 < j) s1 = fma(trow[l + 1], sm.wsum[kt][(l + 1) * 16 + j], s1);
+                }
+                trow[j] = (i < j) ? -tj * (s0 + s1) : ((i == j) ? tj : 0.0);
             }
+        }
+        __syncthreads();
+    };
+
+    // Y_t = T^T W_t (TRANS) or T W_t for tiles t >= T0 into sm.ybuf, one 16 x 16 tile per wave
+    // on the matrix cores.  Ends with a barrier.
+    auto block_y = [&](auto KT, auto T0, auto TRANS) {
+        constexpr int kt = decltype(KT)::value, t0 = decltype(T0)::value;
+        constexpr bool trans = decltype(TRANS)::value;
+        for (int t = t0 + w; t < NCT; t += NW) {
+            d4_t acc = d4_t{0, 0, 0, 0};
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double a = trans ? sm.tstore[kt][4 * q + lr][lc] : sm.tstore[kt][lc][4 * q + lr];
+                const double b = sm.wsum[t][(4 * q + lr) * 16 + lc];
+                acc = mfma4(a, b, acc);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) sm.ybuf[lr + 4 * i][16 * t + lc] = acc[i];
         }
         __syncthreads();
     };
@@ -198,41 +238,47 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
     };
 
     // ---- factorization, block by block ---------------------------------------------------
-    int nstep = 0;
     static_for<0, NCT>([&](auto KT) {
         constexpr int kt = decltype(KT)::value;
         if (16 * kt >= n) return;
-        const int kend = min(16 * kt + 16, n);
-        for (int k = 16 * kt; k < kend; ++k, ++nstep) {
-            const int kk = k - 16 * kt;
-            const int par = nstep & 1;
-            // publish row k of the block (after the previous step's update)
-            {
-                const int rtile = k >> 4;                 // global row tile of row k
-                if (rtile / RT == w && lr == (k & 3)) {
-                    const int rt = rtile - w * RT, ik = (k & 15) >> 2;
-                    double v = 0.0;
+        // the 16 Householder steps of the block, unrolled: row k = 16 kt + kk lives in row tile
+        // kt, i.e. in wave kt % NW, tile slot kt / NW, value kk / 4 of the lanes with lr = kk % 4
+        static_for<0, 16>([&](auto KK) {
+            constexpr int kk = decltype(KK)::value;
+            constexpr int par = kk & 1;
+            constexpr int rtk = kt / NW, ik = kk >> 2;
+            const int k = 16 * kt + kk;
+            if (k >= n) return;
+            const bool own = (w == kt % NW);                  // this wave holds row tile kt
+            if (own && lr == (kk & 3)) sm.rowk[par][lc] = P[rtk][kt][ik];
+            // pivot column x (rows > k) and the partial dots with the block's columns; tiles
+            // above tile kt hold finished rows (x = 0, no update)
+            double xm[RT][4];
+            double d0 = 0.0, d1 = 0.0;
 #pragma unroll
-                    for (int r2 = 0; r2 < RT; ++r2)
+            for (int rt = 0; rt < RT; ++rt) {
+                const int gt = rt * NW + w;
+                if (gt > kt) {
 #pragma unroll
-                        for (int i = 0; i < 4; ++i)
-                            if (r2 == rt && i == ik) v = P[r2][kt][i];
-                    sm.rowk[par][lc] = v;
+                    for (int i = 0; i < 4; ++i) {
+                        xm[rt][i] = bcast16<kk>(P[rt][kt][i]);
+                        if (i & 1) d1 = fma(xm[rt][i], P[rt][kt][i], d1);
+                        else d0 = fma(xm[rt][i], P[rt][kt][i], d0);
+                    }
+                } else if (gt == kt) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const double xv = bcast16<kk>(P[rt][kt][i]);
+                        xm[rt][i] = (lr + 4 * i > kk) ? xv : 0.0;
+                        if (i & 1) d1 = fma(xm[rt][i], P[rt][kt][i], d1);
+                        else d0 = fma(xm[rt][i], P[rt][kt][i], d0);
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) xm[rt][i] = 0.0;
                 }
             }
-            // pivot column x (rows > k) and the partial dots with the block's columns
-            double xm[RT][4];
-            double d = 0.0;
-#pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const double xv = bcast16(P[rt][kt][i], kk);
-                    xm[rt][i] = (row_of(rt, i) > k) ? xv : 0.0;
-                    d = fma(xm[rt][i], P[rt][kt][i], d);
-                }
-            d += __shfl_xor(d, 16, 64);
-            d += __shfl_xor(d, 32, 64);
+            const double d = sum_xor32(sum_xor16(d0 + d1));
             if (lr == 0) sm.part[par][w][lc] = d;
             __syncthreads();
             double s2 = 0.0, pc = 0.0;
@@ -256,14 +302,20 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
                 coef = tau * (sm.rowk[par][lc] + inv * pc) * inv;
             }
 #pragma unroll
-            for (int rt = 0; rt < RT; ++rt)
+            for (int rt = 0; rt < RT; ++rt) {
+                const int gt = rt * NW + w;
+                if (gt > kt) {
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int r = row_of(rt, i);
-                    const double x = (r == k) ? u : xm[rt][i];
-                    P[rt][kt][i] = fma(-coef, x, P[rt][kt][i]);
+                    for (int i = 0; i < 4; ++i) P[rt][kt][i] = fma(-coef, xm[rt][i], P[rt][kt][i]);
+                } else if (gt == kt) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const double x = (lr + 4 * i == kk) ? u : xm[rt][i];
+                        P[rt][kt][i] = fma(-coef, x, P[rt][kt][i]);
+                    }
                 }
-        }
+            }
+        });
         __syncthreads();      // tau, u of the block visible to every wave
         if constexpr (kt + 1 < NCT) {
             if (16 * (kt + 1) < n) {
@@ -271,16 +323,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
                 gather_v(KT, V);
                 block_products(KT, std::integral_constant<int, kt + 1>{}, std::true_type{}, V);
                 block_t(KT);
-                // Y = T^T W for the trailing tiles
-                for (int e = tid; e < 16 * NCT * 16; e += NT) {
-                    const int m = e / (16 * NCT), c = e - m * (16 * NCT);
-                    if ((c >> 4) <= kt) continue;
-                    double acc = 0.0;
-                    for (int j = 0; j <= m; ++j)
-                        acc = fma(sm.tstore[kt][j][m], sm.wsum[c >> 4][j * 16 + (c & 15)], acc);
-                    sm.ybuf[m][c] = acc;
-                }
-                __syncthreads();
+                block_y(KT, std::integral_constant<int, kt + 1>{}, std::true_type{});
                 block_update(std::integral_constant<int, kt + 1>{}, V);
             }
         }
@@ -320,16 +363,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
             for (int i = 0; i < 4; ++i)
                 P[rt][kt][i] = (row_of(rt, i) == 16 * kt + lc) ? 1.0 : 0.0;
         block_products(KT{}, KT{}, std::false_type{}, V);
-        // Y = T W for tiles >= kt
-        for (int e = tid; e < 16 * NCT * 16; e += NT) {
-            const int m = e / (16 * NCT), c = e - m * (16 * NCT);
-            if ((c >> 4) < kt) continue;
-            double acc = 0.0;
-            for (int j = m; j < 16; ++j)
-                acc = fma(sm.tstore[kt][m][j], sm.wsum[c >> 4][j * 16 + (c & 15)], acc);
-            sm.ybuf[m][c] = acc;
-        }
-        __syncthreads();
+        block_y(KT{}, KT{}, std::false_type{});
         block_update(KT{}, V);
         __syncthreads();
     });

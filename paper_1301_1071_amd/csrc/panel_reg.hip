@@ -26,10 +26,10 @@ k_factor_blk(int64_t rows, int n, const double *__restrict__ X, int64_t ldx,
 }
 
 // Panel shapes of the blocked FP64 kernel (4 waves, two work-groups per CU without spills):
-// 256 rows for n > 32, 384 for n <= 32, 512 for n <= 16.
+// 256 rows for n > 32, 384 for n <= 32.
 template <int NCT> struct BlkShape {
     static constexpr int NW = 4;
-    static constexpr int RT = (NCT >= 3) ? 4 : (NCT == 2 ? 6 : 8);
+    static constexpr int RT = (NCT >= 3) ? 4 : 6;
     static constexpr int B = NW * RT * 16;
 };
 
