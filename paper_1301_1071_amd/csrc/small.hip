@@ -3,8 +3,8 @@
 // Sec. III-B: the single reduce task ends with R~; the factorization with a positive diagonal is
 // unique for full-rank A (Sec. I), so R = D R~ with D = diag(sign(R~_jj)), sign(0) = +1, and the
 // step-3 blocks become Q2_p D.  For the SVD variant the reduce task also computes R = U_R S V^T
-// ("computing its SVD is cheap" -- the method is not named): one-sided Jacobi (Hestenes), columns
-// rotated until pairwise orthogonal, in parallel round-robin order.  U_R is passed down the tree
+// ("computing its SVD is cheap" -- the method is not named): one-sided Jacobi (Hestenes) on R^T,
+// columns rotated until pairwise orthogonal, in parallel round-robin order.  U_R is passed down the tree
 // so that U = Q U_R comes out of step 3 in the same pass as Q.
 #include "tsqr_internal.h"
 
@@ -17,6 +17,20 @@ constexpr int kSmallLdsLimit = 150 * 1024;
 __device__ __forceinline__ int rr_player(int pos, int r, int np)
 {
     return pos == 0 ? 0 : 1 + (pos - 1 + r) % (np - 1);
+}
+
+// reciprocal and reciprocal square root: hardware estimate plus two Newton steps (a few ulp)
+__device__ __forceinline__ double rcp_nr(double x)
+{
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+}
+__device__ __forceinline__ double rsqrt_nr(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    y = y * fma(-0.5 * x * y, y, 1.5);
+    return y * fma(-0.5 * x * y, y, 1.5);
 }
 
 constexpr int kSvdThreads = 1024;   // 16 waves: 64 groups of 16 lanes, one column pair each
@@ -69,9 +83,13 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
     if (want_u || S != nullptr) {
         double *gG = use_lds ? sm : G;                     // column-major n x n
         double *gV = use_lds ? sm + (size_t)n * n : Vw;
+        // one-sided Jacobi on R^T (column r of R^T is row r of R): R^T J = G with orthogonal
+        // columns, so R = J diag(|g|) (G diag(|g|)^{-1})^T, i.e. U_R = J and V = G / |g|.
+        // Rotating the rows of the triangular R converges in far fewer sweeps than rotating its
+        // columns when R is ill conditioned.
         for (int e = tid; e < n * n; e += nth) {
             const int r = e / n, c = e - r * n;
-            gG[(int64_t)c * n + r] = (c >= r) ? d_s[r] * Rt[e] : 0.0;
+            gG[(int64_t)r * n + c] = (c >= r) ? d_s[r] * Rt[e] : 0.0;
             gV[(int64_t)c * n + r] = (r == c) ? 1.0 : 0.0;
         }
         const int np = n + (n & 1);                    // players of the round-robin tournament
@@ -79,6 +97,7 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
         const int grp = tid >> 4, gl = tid & 15;       // 16-lane group and lane within it
         const int ngrp = nth >> 4;
         const double tol = 1e-15 * (double)n;
+        const double tol2 = tol * tol;
         for (int sweep = 0; sweep < 60; ++sweep) {
             __syncthreads();
             if (tid == 0) s_rot = 0;
@@ -103,11 +122,11 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
                     al = group16_sum(al);
                     be = group16_sum(be);
                     ga = group16_sum(ga);
-                    if (ga != 0.0 && fabs(ga) > tol * sqrt(al * be)) {
-                        const double zeta = (be - al) / (2.0 * ga);
-                        const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) /
-                                          (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-                        const double cs = 1.0 / sqrt(1.0 + tt * tt);
+                    if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
+                        const double zeta = 0.5 * (be - al) * rcp_nr(ga);
+                        const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) *
+                                          rcp_nr(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+                        const double cs = rsqrt_nr(fma(tt, tt, 1.0));
                         const double sn = cs * tt;
                         double *vp = gV + (int64_t)p * n, *vq = gV + (int64_t)q * n;
 #pragma unroll
@@ -142,27 +161,25 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
             perm[rank] = c;
         }
         __syncthreads();
+        // gauge: the largest-magnitude entry of each v_k = g_c / |g_c| is positive
         for (int o = tid; o < n; o += nth) {
             const int c = perm[o];
             int imax = 0;
             double vmax = -1.0;
             for (int i = 0; i < n; ++i) {
-                const double a = fabs(gV[(int64_t)c * n + i]);
+                const double a = fabs(gG[(int64_t)c * n + i]);
                 if (a > vmax) { vmax = a; imax = i; }
             }
-            s_sg[o] = (gV[(int64_t)c * n + imax] < 0.0) ? -1.0 : 1.0;
+            s_sg[o] = (gG[(int64_t)c * n + imax] < 0.0) ? -1.0 : 1.0;
             if (S) S[o] = s_sv[c];
         }
         __syncthreads();
         for (int e = tid; e < n * n; e += nth) {
             const int i = e / n, o = e - i * n;
             const int c = perm[o];
-            if (V) V[(int64_t)i * ldv + o] = s_sg[o] * gV[(int64_t)c * n + i];
-            if (want_u) {
-                const double s = s_sv[c];
-                const double u = (s > 0.0) ? s_sg[o] * gG[(int64_t)c * n + i] / s : 0.0;
-                Wtop[(int64_t)i * k + kq + o] = d_s[i] * u;
-            }
+            const double s = s_sv[c];
+            if (V) V[(int64_t)i * ldv + o] = (s > 0.0) ? s_sg[o] * gG[(int64_t)c * n + i] / s : 0.0;
+            if (want_u) Wtop[(int64_t)i * k + kq + o] = d_s[i] * s_sg[o] * gV[(int64_t)c * n + i];
         }
     }
     if (tid == 0) *info = s_nonfinite ? -1 : (s_zero == 0x7fffffff ? 0 : s_zero + 1);
