@@ -6,15 +6,25 @@ namespace {
 
 using namespace mfmaapply;
 
+// One work-group per (panel, 16 NT-column slice).  The 1-D grid keeps the ny slices of one
+// panel on the same XCD (work-group b runs on XCD b % 8): b = 8 ny g + 8 y + x covers panel
+// 8 g + x, slice y, so a panel's Q1 rows are read from HBM once and served from that XCD's L2
+// to the other slices.
 template <typename T, typename To, int NT>
 __global__ void __launch_bounds__(kWaves * 64)
 k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, int64_t ldq,
              const double *__restrict__ W, int64_t ldw, int64_t wstride, int k,
              To *__restrict__ out0, int64_t ld0, int k0, To *__restrict__ out1, int64_t ld1,
-             int accumulate)
+             int accumulate, int64_t panels, int ny)
 {
+    const int64_t bid = blockIdx.x;
+    const int64_t grp = bid / (8 * ny);
+    const int rem = (int)(bid - grp * 8 * ny);
+    const int y = rem >> 3;
+    const int64_t p = grp * 8 + (rem & 7);
+    if (p >= panels) return;
     apply_mfma_panel<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1,
-                                ld1, accumulate, blockIdx.x, blockIdx.y * 16 * NT);
+                                ld1, accumulate, p, y * 16 * NT);
 }
 
 template <typename T, typename To, int NT>
@@ -32,9 +42,11 @@ hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t
         attr_bytes = lds;
     }
     const int64_t panels = ceil_div(rows, b);
-    dim3 grid((unsigned)panels, (unsigned)ceil_div(k, 16 * NT));
-    hipLaunchKernelGGL(kern, grid, dim3(kWaves * 64), lds, st, rows, (int)n, b, (const T *)q1,
-                       ldq, W, ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1, ld1, acc);
+    const int ny = (int)ceil_div(k, 16 * NT);
+    const int64_t blocks = ceil_div(panels, 8) * 8 * ny;
+    hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kWaves * 64), lds, st, rows, (int)n, b,
+                       (const T *)q1, ldq, W, ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1,
+                       ld1, acc, panels, ny);
     return hipGetLastError();
 }
 
@@ -43,17 +55,15 @@ hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t 
                         const double *W, int64_t ldw, int64_t wstride, int k, void *out0,
                         int64_t ld0, int k0, void *out1, int64_t ld1, int acc, hipStream_t st)
 {
-    // one pass covers up to 16 * NT output columns; NT = 8 keeps W's LDS image <= 128 KiB
+    // one work-group covers up to 16 * NT output columns
     const int tiles = (int)ceil_div(k, 16);
 #define TSQR_NT(NT)                                                                          \
     return apply_mfma_nt<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1, \
                                     ld1, acc, st)
-    // FP64 with n > 64: W's LDS image is capped at 4 tiles per pass (LDS stays under 140 KiB)
-    if (sizeof(T) == 8 && n > 64 && tiles > 2) TSQR_NT(4);
+    // at most 4 tiles (64 columns) per work-group: wider outputs take several slices, which
+    // keeps the LDS image of W small enough for three work-groups per CU
     if (tiles <= 2) TSQR_NT(2);
-    if (tiles <= 4) TSQR_NT(4);
-    if (tiles <= 7) TSQR_NT(7);
-    TSQR_NT(8);
+    TSQR_NT(4);
 #undef TSQR_NT
 }
 

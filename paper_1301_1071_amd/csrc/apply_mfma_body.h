@@ -72,14 +72,31 @@ __device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
     const int64_t rb = p * (int64_t)b;
     const int nr = (int)min((int64_t)b, rows - rb);
     const int nblk = (nr + 15) >> 4;
-    for (int blk = w; blk < nblk; blk += kWaves) {
+    const int jl = j0 + (lane & 15);
+    // The 16 x n blocks of Q1 are fetched one block ahead into registers (lane owns columns
+    // lane and lane + 64 of every row), so the next block's loads are in flight during this
+    // block's products; each block is then staged through this wave's LDS rows.
+    T pre[16], pre2[16];
+    auto fetch = [&](int blk) {
         const int r0 = blk * 16;
         const int cnt = min(16, nr - r0);
         const T *src = q1 + (rb + r0) * ldq;
-        for (int e = lane; e < 16 * n; e += 64) {
-            const int r = e / n, c = e - r * n;
-            as[r * LDA + c] = (r < cnt) ? src[(int64_t)r * ldq + c] : T(0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            pre[r] = (r < cnt && lane < n) ? src[(int64_t)r * ldq + lane] : T(0);
+            pre2[r] = (r < cnt && lane + 64 < n) ? src[(int64_t)r * ldq + lane + 64] : T(0);
         }
+    };
+    if (w < nblk) fetch(w);
+    for (int blk = w; blk < nblk; blk += kWaves) {
+        const int r0 = blk * 16;
+        const int cnt = min(16, nr - r0);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+            if (lane < n) as[r * LDA + lane] = pre[r];
+            if (lane + 64 < n) as[r * LDA + lane + 64] = pre2[r];
+        }
+        if (blk + kWaves < nblk) fetch(blk + kWaves);
         // the wave reads back what its own lanes wrote: LDS operations of a wave are ordered
         acc_t acc[NT];
 #pragma unroll
@@ -90,27 +107,31 @@ __device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
 #pragma unroll
             for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::run(a, wk[t * 64], acc[t]);
         }
+        // results: row pointers once per block, then a column offset per tile
+        To *o0[4], *o1[4];
+        bool rok[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int r = Mfma<T>::row(lane, i);
+            rok[i] = r < cnt;
+            const int64_t gr = rb + r0 + (rok[i] ? r : 0);
+            o0[i] = out0 + gr * ld0;
+            o1[i] = out1 ? out1 + gr * ld1 - k0 : nullptr;
+        }
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int j = j0 + 16 * t + (lane & 15);
+            const int j = jl + 16 * t;
+            if (j >= k) continue;
+            const bool first = j < k0;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int r = Mfma<T>::row(lane, i);
-                if (r < cnt) {
-                    const int64_t gr = rb + r0 + r;
-                    if (j < k0) {
-                        To *o = out0 + gr * ld0 + j;
-                        *o = accumulate ? (To)(acc[t][i] + (T)*o) : (To)acc[t][i];
-                    } else if (j < k) {
-                        To *o = out1 + gr * ld1 + (j - k0);
-                        *o = accumulate ? (To)(acc[t][i] + (T)*o) : (To)acc[t][i];
-                    }
-                }
+                if (!rok[i]) continue;
+                To *o = (first ? o0[i] : o1[i]) + j;
+                *o = accumulate ? (To)(acc[t][i] + (T)*o) : (To)acc[t][i];
             }
         }
     }
 }
-
 
 // Dynamic LDS of one work-group for n columns and NT output tiles.
 template <typename T, int NT> inline size_t apply_lds_bytes(int64_t n)
