@@ -104,7 +104,10 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         const int req = (L == 0 && o) ? o->panel_rows : 0;
         const int bl = lds_panel_rows_max(n, lv.dtype);
         const int breg = reg_panel_rows(n, lv.dtype);
-        if (req == 0 && (rows <= breg || (ceil_div(rows, breg) * n < rows && rows > 8 * n))) {
+        // FP64 levels run the blocked kernel, whose panels always shrink a stack of more than
+        // one panel (b >= 2n); the FP32 register kernel keeps a single LDS panel for short stacks
+        const bool shrinks = ceil_div(rows, breg) * n < rows;
+        if (req == 0 && (rows <= breg || (shrinks && (lv.dtype == F64 || rows > 8 * n)))) {
             // default: register-resident panels of the register kernel's height
             lv.reg = true;
             lv.global = false;

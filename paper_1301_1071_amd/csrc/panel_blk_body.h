@@ -75,18 +75,14 @@ template <int I, int N, typename F> __device__ __forceinline__ void static_for(F
     }
 }
 
-template <int NCT, int RT, int NW> struct BlkCfg {
-    static constexpr int B = NW * RT * 16;
-    static constexpr int NCOL = NCT * 16;
-};
-
-// LDS of one work-group
-template <int NCT, int RT, int NW> struct BlkSmem {
+// LDS of one work-group (dynamic: more than 64 KiB for the widest panels).  TC = column tiles
+// whose per-wave products are reduced at a time.
+template <int NCT, int RT, int NW, int TC> struct BlkSmem {
     double part[2][NW][16];          // per-step partial dots of the block's columns
     double rowk[2][16];              // pivot row k restricted to the block
     double tau[NCT * 16], u[NCT * 16], beta[NCT * 16];
     union {
-        double red[NW][NCT][256];    // per-wave partial products (G, W) before the wave sum
+        double red[NW][TC][256];     // per-wave partial products (G, W) before the wave sum
         double vt[NW][16][17];       // one row tile of V per wave, row-major (A operand of V Y)
     };
     double wsum[NCT][256];           // summed products: slot kt = G = V^T V, slot t = W of tile t
@@ -94,14 +90,15 @@ template <int NCT, int RT, int NW> struct BlkSmem {
     double ybuf[16][NCT * 16 + 1];   // Y = T^T W (or T W) for the trailing tiles
 };
 
-template <int NCT, int RT, int NW>
+template <int NCT, int RT, int NW, int TC>
 __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const double *__restrict__ X,
                                                  int64_t ldx, double *__restrict__ q1,
                                                  double *__restrict__ S, int64_t p)
 {
     constexpr int B = NW * RT * 16;
     constexpr int NT = NW * 64;
-    __shared__ BlkSmem<NCT, RT, NW> sm;
+    extern __shared__ __align__(16) unsigned char blk_smem_raw[];
+    BlkSmem<NCT, RT, NW, TC> &sm = *reinterpret_cast<BlkSmem<NCT, RT, NW, TC> *>(blk_smem_raw);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -144,36 +141,47 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
     };
 
     // W_t = V^T A[:, tile t] for tiles t >= T0 into wsum[t], and with WITH_G also G = V^T V into
-    // wsum[KT] (then T0 > KT); summed over the waves in a fixed order.  Ends with a barrier.
+    // wsum[KT] (then T0 > KT); summed over the waves in a fixed order, TC products at a time.
+    // Ends with a barrier.
     auto block_products = [&](auto KT, auto T0, auto WITH_G, const double (&V)[RT][4]) {
         constexpr int kt = decltype(KT)::value, t0 = decltype(T0)::value;
         constexpr bool with_g = decltype(WITH_G)::value;
-        d4_t acc[NCT];
+        constexpr int L = (with_g ? 1 : 0) + (NCT - t0);          // products: [G,] tiles t0..
+        constexpr int NCH = (L + TC - 1) / TC;
+        static_for<0, NCH>([&](auto CH) {
+            constexpr int c0 = decltype(CH)::value * TC;
+            // product e of the list: G for e == 0 with_g, else tile t0 + e - with_g
+            d4_t acc[TC];
 #pragma unroll
-        for (int t = 0; t < NCT; ++t) acc[t] = d4_t{0, 0, 0, 0};
+            for (int s = 0; s < TC; ++s) acc[s] = d4_t{0, 0, 0, 0};
 #pragma unroll
-        for (int rt = 0; rt < RT; ++rt)
+            for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                if constexpr (with_g) acc[kt] = mfma4(V[rt][i], V[rt][i], acc[kt]);
+                for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int t = t0; t < NCT; ++t) acc[t] = mfma4(V[rt][i], P[rt][t][i], acc[t]);
+                    for (int s = 0; s < TC; ++s) {
+                        const int e = c0 + s;
+                        if (e >= L) continue;
+                        if (with_g && e == 0) acc[s] = mfma4(V[rt][i], V[rt][i], acc[s]);
+                        else acc[s] = mfma4(V[rt][i], P[rt][t0 + e - (with_g ? 1 : 0)][i], acc[s]);
+                    }
+#pragma unroll
+            for (int s = 0; s < TC; ++s)
+                if (c0 + s < L)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) sm.red[w][s][(lr + 4 * i) * 16 + lc] = acc[s][i];
+            __syncthreads();
+            for (int e2 = tid; e2 < TC * 256; e2 += NT) {
+                const int s = e2 >> 8, e = c0 + s;
+                if (e >= L) continue;
+                const int slot = (with_g && e == 0) ? kt : t0 + e - (with_g ? 1 : 0);
+                double sum = 0.0;
+#pragma unroll
+                for (int ww = 0; ww < NW; ++ww) sum += sm.red[ww][s][e2 & 255];
+                sm.wsum[slot][e2 & 255] = sum;
             }
-#pragma unroll
-        for (int t = 0; t < NCT; ++t)
-            if (t >= t0 || (with_g && t == kt))
-#pragma unroll
-                for (int i = 0; i < 4; ++i) sm.red[w][t][(lr + 4 * i) * 16 + lc] = acc[t][i];
-        __syncthreads();
-        for (int e = tid; e < NCT * 256; e += NT) {
-            const int t = e >> 8;
-            if (!(t >= t0 || (with_g && t == kt))) continue;
-            double s = 0.0;
-#pragma unroll
-            for (int ww = 0; ww < NW; ++ww) s += sm.red[ww][t][e & 255];
-            sm.wsum[t][e & 255] = s;
-        }
-        __syncthreads();
+            __syncthreads();
+        });
     };
 
     // T of block KT (Q_blk = H_1 ... H_16 = I - V T V^T) from G = wsum[KT] = V^T V by the

@@ -17,21 +17,25 @@ k_factor_reg(int64_t rows, int n, const Tin *__restrict__ X, int64_t ldx, T *__r
     factor_reg_panel<Tin, T, NC, CPL, RW, NW>(rows, n, X, ldx, q1, S, blockIdx.x);
 }
 
-template <int NCT, int RT, int NW>
-__global__ void __launch_bounds__(NW * 64, 2)
+// Panel shapes of the blocked FP64 kernel (no spills, two work-groups per CU up to n = 64):
+// 4 waves with 256 rows for 32 < n <= 64, 384 rows for n <= 32; 8 waves with 256 rows for
+// 64 < n <= 128 (one work-group per CU).
+template <int NCT> struct BlkShape {
+    static constexpr int NW = (NCT <= 4) ? 4 : 8;
+    static constexpr int RT = (NCT <= 2) ? 6 : ((NCT <= 4) ? 4 : 2);
+    static constexpr int TC = (NCT <= 4) ? NCT : 2;
+    static constexpr int B = NW * RT * 16;
+    static constexpr size_t LDS = sizeof(blkpanel::BlkSmem<NCT, RT, NW, TC>);
+};
+
+template <int NCT>
+__global__ void __launch_bounds__(BlkShape<NCT>::NW * 64, (NCT <= 4) ? 2 : 1)
 k_factor_blk(int64_t rows, int n, const double *__restrict__ X, int64_t ldx,
              double *__restrict__ q1, double *__restrict__ S)
 {
-    blkpanel::factor_blk_panel<NCT, RT, NW>(rows, n, X, ldx, q1, S, blockIdx.x);
+    using C = BlkShape<NCT>;
+    blkpanel::factor_blk_panel<NCT, C::RT, C::NW, C::TC>(rows, n, X, ldx, q1, S, blockIdx.x);
 }
-
-// Panel shapes of the blocked FP64 kernel (4 waves, two work-groups per CU without spills):
-// 256 rows for n > 32, 384 for n <= 32.
-template <int NCT> struct BlkShape {
-    static constexpr int NW = 4;
-    static constexpr int RT = (NCT >= 3) ? 4 : 6;
-    static constexpr int B = NW * RT * 16;
-};
 
 template <int NCT>
 hipError_t factor_blk_launch(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
@@ -39,27 +43,45 @@ hipError_t factor_blk_launch(int64_t rows, int64_t n, const void *X, int64_t ldx
 {
     using C = BlkShape<NCT>;
     const int64_t panels = ceil_div(rows, C::B);
-    hipLaunchKernelGGL((k_factor_blk<NCT, C::RT, C::NW>), dim3((unsigned)panels),
-                       dim3(C::NW * 64), 0, st, rows, (int)n, (const double *)X, ldx,
-                       (double *)q1, S);
+    static bool attr_set = false;
+    if (C::LDS > 64 * 1024 && !attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_factor_blk<NCT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_factor_blk<NCT>), dim3((unsigned)panels), dim3(C::NW * 64), C::LDS, st,
+                       rows, (int)n, (const double *)X, ldx, (double *)q1, S);
     return hipGetLastError();
 }
 
 hipError_t factor_blk_dispatch(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
                                double *S, hipStream_t st)
 {
-    if (n <= 16) return factor_blk_launch<1>(rows, n, X, ldx, q1, S, st);
-    if (n <= 32) return factor_blk_launch<2>(rows, n, X, ldx, q1, S, st);
-    if (n <= 48) return factor_blk_launch<3>(rows, n, X, ldx, q1, S, st);
-    return factor_blk_launch<4>(rows, n, X, ldx, q1, S, st);
+    switch ((n + 15) / 16) {
+    case 1: return factor_blk_launch<1>(rows, n, X, ldx, q1, S, st);
+    case 2: return factor_blk_launch<2>(rows, n, X, ldx, q1, S, st);
+    case 3: return factor_blk_launch<3>(rows, n, X, ldx, q1, S, st);
+    case 4: return factor_blk_launch<4>(rows, n, X, ldx, q1, S, st);
+    case 5: return factor_blk_launch<5>(rows, n, X, ldx, q1, S, st);
+    case 6: return factor_blk_launch<6>(rows, n, X, ldx, q1, S, st);
+    case 7: return factor_blk_launch<7>(rows, n, X, ldx, q1, S, st);
+    default: return factor_blk_launch<8>(rows, n, X, ldx, q1, S, st);
+    }
 }
 
 int blk_panel_rows(int64_t n)
 {
-    if (n <= 16) return BlkShape<1>::B;
-    if (n <= 32) return BlkShape<2>::B;
-    if (n <= 48) return BlkShape<3>::B;
-    return BlkShape<4>::B;
+    switch ((n + 15) / 16) {
+    case 1: return BlkShape<1>::B;
+    case 2: return BlkShape<2>::B;
+    case 3: return BlkShape<3>::B;
+    case 4: return BlkShape<4>::B;
+    case 5: return BlkShape<5>::B;
+    case 6: return BlkShape<6>::B;
+    case 7: return BlkShape<7>::B;
+    default: return BlkShape<8>::B;
+    }
 }
 
 // out rows of panel p = Q1_p (b x n) * W_p (n x k).  Q1 rows are staged through LDS in chunks
@@ -206,7 +228,7 @@ hipError_t apply_staged_dispatch(int64_t rows, int64_t n, int b, const void *q1,
 
 int reg_panel_rows(int64_t n, int dtype)
 {
-    if (dtype == F64 && n <= 64) return blk_panel_rows(n);
+    if (dtype == F64) return blk_panel_rows(n);
     return reg_panel_rows_variant(n, dtype, 0);
 }
 
@@ -214,7 +236,7 @@ hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, c
                              int64_t ldx, void *q1, double *S, hipStream_t st)
 {
     if (dtype == F64) {
-        if (in_dtype == F64 && n <= 64) return factor_blk_dispatch(rows, n, X, ldx, q1, S, st);
+        if (in_dtype == F64) return factor_blk_dispatch(rows, n, X, ldx, q1, S, st);
         if (in_dtype == F64) return factor_reg_dispatch<double, double>(rows, n, X, ldx, q1, S, st);
         return factor_reg_dispatch<float, double>(rows, n, X, ldx, q1, S, st);
     }
