@@ -192,11 +192,12 @@ tsqr_status tsqr_qr_batched(tsqr_batch_plan plan, const void *const *d_A, void *
 
 /*
  * Panel-height table used by batched plans, one entry per (dtype, width class n <= 4, 8, 16,
- * 32, 64).  Each class has up to three register-panel variants (0 = default height, 1 and 2 =
- * half height with half the rows per lane or half the waves); tsqr_tune_variants lists their
- * heights for width n (0 = not usable: a panel must hold at least 3n rows).  The autotuner
- * (paper_1301_1071_amd/autotune.py) times them and records its choice with tsqr_tune_set.
- * Set the table before creating plans; it is process-wide.
+ * 32, 64).  Each class has up to three panel variants: in FP64 (blocked panels) 0 = default
+ * height, 1 = half height, 2 = 512 rows (n <= 16 only); in FP32 (register panels) 0 = default,
+ * 1 and 2 = half height with half the rows per lane or half the waves.  tsqr_tune_variants lists
+ * their heights for width n (0 = not usable: a panel must hold at least 3n rows, or the variant
+ * repeats the default).  The autotuner (paper_1301_1071_amd/autotune.py) times them and records
+ * its choice with tsqr_tune_set.  Set the table before creating plans; it is process-wide.
  */
 tsqr_status tsqr_tune_set(int32_t dtype, int64_t n, int32_t variant);
 tsqr_status tsqr_tune_get(int32_t dtype, int64_t n, int32_t *variant, int32_t *panel_rows);

@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "apply_mfma_body.h"
+#include "panel_blk_body.h"
 #include "panel_reg_body.h"
 
 namespace tsqr {
@@ -78,6 +79,32 @@ k_factor_batched(const FactorTask *__restrict__ tasks, int ntasks, const void *c
                                                      blk - t.first_block);
 }
 
+// FP64 panels of the batched form: the blocked kernel, variant V of the width class NCT
+// (V = 0 default height, 1 = half the row tiles per wave, 2 = 512 rows for n <= 16)
+template <int NCT, int V> struct BlkShapeB {
+    static constexpr int NW = 4;
+    static constexpr int RT0 = (NCT <= 2) ? 6 : 4;
+    static constexpr int RT = (V == 1) ? RT0 / 2 : ((V == 2 && NCT == 1) ? 8 : RT0);
+    static constexpr int TC = NCT;
+    static constexpr int B = NW * RT * 16;
+    static constexpr size_t LDS = sizeof(blkpanel::BlkSmem<NCT, RT, NW, TC>);
+};
+
+template <int NCT, int V>
+__global__ void __launch_bounds__(256, 2)
+k_factor_blk_batched(const FactorTask *__restrict__ tasks, int ntasks, const void *const *A,
+                     char *__restrict__ ws)
+{
+    using C = BlkShapeB<NCT, V>;
+    const int64_t blk = blockIdx.x;
+    const FactorTask t = tasks[find_task(tasks, ntasks, blk)];
+    const double *X = t.x_off < 0 ? (const double *)A[t.mat] : (const double *)(ws + t.x_off);
+    blkpanel::factor_blk_panel<NCT, C::RT, C::NW, C::TC>(t.rows, t.n, X, t.ldx,
+                                                         (double *)(ws + t.q1_off),
+                                                         (double *)(ws + t.s_off),
+                                                         blk - t.first_block);
+}
+
 template <typename T, typename To, int NT>
 __global__ void __launch_bounds__(mfmaapply::kWaves * 64)
 k_apply_batched(const ApplyTask *__restrict__ tasks, int ntasks, void *const *Q,
@@ -135,10 +162,63 @@ int width_class(int64_t n)
     return n <= 4 ? 0 : n <= 8 ? 1 : n <= 16 ? 2 : n <= 32 ? 3 : 4;
 }
 
-// A variant is usable for width n if its panels shrink every tree level (b >= 3n).
+// Panel height of variant v for width n: FP64 panels run the blocked kernel, FP32 panels the
+// register kernel.
+template <int V> int blk_rows_b(int64_t n)
+{
+    switch ((n + 15) / 16) {
+    case 1: return BlkShapeB<1, V>::B;
+    case 2: return BlkShapeB<2, V>::B;
+    case 3: return BlkShapeB<3, V>::B;
+    default: return BlkShapeB<4, V>::B;
+    }
+}
+
+int batch_panel_rows(int64_t n, int dtype, int v)
+{
+    if (dtype == F32) return reg_panel_rows_variant(n, dtype, v);
+    return v == 1 ? blk_rows_b<1>(n) : (v == 2 ? blk_rows_b<2>(n) : blk_rows_b<0>(n));
+}
+
+// A variant is usable for width n if its panels shrink every tree level (b >= 3n) and it
+// differs from the default height (variant 2 only exists for n <= 16 in FP64).
 bool variant_ok(int64_t n, int dtype, int v)
 {
-    return v >= 0 && v <= 2 && reg_panel_rows_variant(n, dtype, v) >= 3 * n;
+    if (v < 0 || v > 2) return false;
+    if (v > 0 && batch_panel_rows(n, dtype, v) == batch_panel_rows(n, dtype, 0) &&
+        dtype == F64)
+        return false;
+    return batch_panel_rows(n, dtype, v) >= 3 * n;
+}
+
+template <int NCT, int V>
+hipError_t factor_blk_batched_cv(const FactorTask *tasks, int nt, int64_t blocks,
+                                 const void *const *A, char *ws, hipStream_t st)
+{
+    using C = BlkShapeB<NCT, V>;
+    hipLaunchKernelGGL((k_factor_blk_batched<NCT, V>), dim3((unsigned)blocks), dim3(C::NW * 64),
+                       C::LDS, st, tasks, nt, A, ws);
+    return hipGetLastError();
+}
+
+template <int NCT>
+hipError_t factor_blk_batched_c(int v, const FactorTask *tasks, int nt, int64_t blocks,
+                                const void *const *A, char *ws, hipStream_t st)
+{
+    if (v == 1) return factor_blk_batched_cv<NCT, 1>(tasks, nt, blocks, A, ws, st);
+    if (v == 2) return factor_blk_batched_cv<NCT, 2>(tasks, nt, blocks, A, ws, st);
+    return factor_blk_batched_cv<NCT, 0>(tasks, nt, blocks, A, ws, st);
+}
+
+hipError_t factor_blk_batched(int64_t n, int v, const FactorTask *tasks, int nt, int64_t blocks,
+                              const void *const *A, char *ws, hipStream_t st)
+{
+    switch ((n + 15) / 16) {
+    case 1: return factor_blk_batched_c<1>(v, tasks, nt, blocks, A, ws, st);
+    case 2: return factor_blk_batched_c<2>(v, tasks, nt, blocks, A, ws, st);
+    case 3: return factor_blk_batched_c<3>(v, tasks, nt, blocks, A, ws, st);
+    default: return factor_blk_batched_c<4>(v, tasks, nt, blocks, A, ws, st);
+    }
 }
 
 // ---- launch dispatch on the width class and variant ----------------------------------------
@@ -250,7 +330,7 @@ tsqr_status tsqr_tune_get(int32_t dtype, int64_t n, int32_t *variant, int32_t *p
     int v = g_tune[dt][width_class(n)];
     if (!variant_ok(n, dt, v)) v = 0;
     *variant = v;
-    *panel_rows = reg_panel_rows_variant(n, dt, v);
+    *panel_rows = batch_panel_rows(n, dt, v);
     return TSQR_OK;
 }
 
@@ -263,7 +343,7 @@ tsqr_status tsqr_tune_variants(int32_t dtype, int64_t n, int32_t max, int32_t *p
     const int dt = dtype == TSQR_DTYPE_F32 ? F32 : F64;
     int c = 0;
     for (int v = 0; v <= 2; ++v) {
-        const int b = variant_ok(n, dt, v) ? reg_panel_rows_variant(n, dt, v) : 0;
+        const int b = variant_ok(n, dt, v) ? batch_panel_rows(n, dt, v) : 0;
         if (c < max) panel_rows[c] = b;
         ++c;
     }
@@ -297,7 +377,7 @@ tsqr_status tsqr_batch_plan_create(int32_t batch, const int64_t *m, const int64_
     auto pick_variant = [&](int64_t w, int ldt, bool explicit_rows, int *v) -> tsqr_status {
         if (explicit_rows && opts && opts->panel_rows > 0) {
             for (int c = 0; c <= 2; ++c)
-                if (variant_ok(w, ldt, c) && reg_panel_rows_variant(w, ldt, c) == opts->panel_rows) {
+                if (variant_ok(w, ldt, c) && batch_panel_rows(w, ldt, c) == opts->panel_rows) {
                     *v = c;
                     return TSQR_OK;
                 }
@@ -331,8 +411,8 @@ tsqr_status tsqr_batch_plan_create(int32_t batch, const int64_t *m, const int64_
             variant_of[w] = v;
             variant_tree[w] = vt;
         }
-        const int64_t B0 = reg_panel_rows_variant(w, dt, variant_of[w]);
-        const int64_t Bt = reg_panel_rows_variant(w, F64, variant_tree[w]);
+        const int64_t B0 = batch_panel_rows(w, dt, variant_of[w]);
+        const int64_t Bt = batch_panel_rows(w, F64, variant_tree[w]);
         int64_t rows = m[i];
         for (int L = 0;; ++L) {
             if (L >= kMaxLevels) return TSQR_ERR_UNSUPPORTED;
@@ -489,7 +569,7 @@ tsqr_status tsqr_qr_batched(tsqr_batch_plan plan, const void *const *d_A, void *
                 TSQR_HIP_CHECK((factor_batched<float, float>(la.n, la.variant, t, la.ntasks,
                                                              la.blocks, d_A, w, st)));
             else
-                TSQR_HIP_CHECK((factor_batched<double, double>(la.n, la.variant, t, la.ntasks,
+                TSQR_HIP_CHECK((factor_blk_batched(la.n, la.variant, t, la.ntasks,
                                                                la.blocks, d_A, w, st)));
         } else if (la.kind == LK_FINAL) {
             ProfScope ps(PC_FINALIZE, st);
