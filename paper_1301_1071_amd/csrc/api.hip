@@ -104,10 +104,12 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         const int req = (L == 0 && o) ? o->panel_rows : 0;
         const int bl = lds_panel_rows_max(n, lv.dtype);
         const int breg = reg_panel_rows(n, lv.dtype);
-        // FP64 levels run the blocked kernel, whose panels always shrink a stack of more than
-        // one panel (b >= 2n); the FP32 register kernel keeps a single LDS panel for short stacks
+        // levels run the blocked kernel, whose panels always shrink a stack of more than one
+        // panel (b >= 2n); short FP32 stacks and FP32 panels wider than 64 columns use one LDS
+        // (or global-memory) panel instead
         const bool shrinks = ceil_div(rows, breg) * n < rows;
-        if (req == 0 && (rows <= breg || (shrinks && (lv.dtype == F64 || rows > 8 * n)))) {
+        const bool blk_ok = !(lv.dtype == F32 && n > 64);    // FP32 blocked panels: n <= 64
+        if (req == 0 && blk_ok && (rows <= breg || (shrinks && (lv.dtype == F64 || rows > 8 * n)))) {
             // default: register-resident panels of the register kernel's height
             lv.reg = true;
             lv.global = false;

@@ -18,7 +18,6 @@
 
 #include "apply_mfma_body.h"
 #include "panel_blk_body.h"
-#include "panel_reg_body.h"
 
 namespace tsqr {
 namespace {
@@ -66,20 +65,7 @@ __device__ __forceinline__ int find_task(const Task *__restrict__ t, int nt, int
     return lo;
 }
 
-template <typename Tin, typename T, int NC, int RW, int NW>
-__global__ void __launch_bounds__(NW * 64, (NW <= 8) ? 4 : 3)
-k_factor_batched(const FactorTask *__restrict__ tasks, int ntasks, const void *const *A,
-                 char *__restrict__ ws)
-{
-    const int64_t blk = blockIdx.x;
-    const FactorTask t = tasks[find_task(tasks, ntasks, blk)];
-    const Tin *X = t.x_off < 0 ? (const Tin *)A[t.mat] : (const Tin *)(ws + t.x_off);
-    regpanel::factor_reg_panel<Tin, T, NC, 1, RW, NW>(t.rows, t.n, X, t.ldx, (T *)(ws + t.q1_off),
-                                                     (double *)(ws + t.s_off),
-                                                     blk - t.first_block);
-}
-
-// FP64 panels of the batched form: the blocked kernel, variant V of the width class NCT
+// Panels of the batched form: the blocked kernel, variant V of the width class NCT
 // (V = 0 default height, 1 = half the row tiles per wave, 2 = 512 rows for n <= 16)
 template <int NCT, int V> struct BlkShapeB {
     static constexpr int NW = 4;
@@ -87,10 +73,13 @@ template <int NCT, int V> struct BlkShapeB {
     static constexpr int RT = (V == 1) ? RT0 / 2 : ((V == 2 && NCT == 1) ? 8 : RT0);
     static constexpr int TC = NCT;
     static constexpr int B = NW * RT * 16;
-    static constexpr size_t LDS = sizeof(blkpanel::BlkSmem<NCT, RT, NW, TC>);
+    template <typename T> static constexpr size_t lds()
+    {
+        return sizeof(blkpanel::BlkSmem<T, NCT, RT, NW, TC>);
+    }
 };
 
-template <int NCT, int V>
+template <typename T, int NCT, int V>
 __global__ void __launch_bounds__(256, 2)
 k_factor_blk_batched(const FactorTask *__restrict__ tasks, int ntasks, const void *const *A,
                      char *__restrict__ ws)
@@ -98,11 +87,11 @@ k_factor_blk_batched(const FactorTask *__restrict__ tasks, int ntasks, const voi
     using C = BlkShapeB<NCT, V>;
     const int64_t blk = blockIdx.x;
     const FactorTask t = tasks[find_task(tasks, ntasks, blk)];
-    const double *X = t.x_off < 0 ? (const double *)A[t.mat] : (const double *)(ws + t.x_off);
-    blkpanel::factor_blk_panel<NCT, C::RT, C::NW, C::TC>(t.rows, t.n, X, t.ldx,
-                                                         (double *)(ws + t.q1_off),
-                                                         (double *)(ws + t.s_off),
-                                                         blk - t.first_block);
+    const T *X = t.x_off < 0 ? (const T *)A[t.mat] : (const T *)(ws + t.x_off);
+    blkpanel::factor_blk_panel<T, T, NCT, C::RT, C::NW, C::TC>(t.rows, t.n, X, t.ldx,
+                                                               (T *)(ws + t.q1_off),
+                                                               (double *)(ws + t.s_off),
+                                                               blk - t.first_block);
 }
 
 template <typename T, typename To, int NT>
@@ -162,8 +151,7 @@ int width_class(int64_t n)
     return n <= 4 ? 0 : n <= 8 ? 1 : n <= 16 ? 2 : n <= 32 ? 3 : 4;
 }
 
-// Panel height of variant v for width n: FP64 panels run the blocked kernel, FP32 panels the
-// register kernel.
+// Panel height of variant v for width n (the same for FP64 and FP32 panels).
 template <int V> int blk_rows_b(int64_t n)
 {
     switch ((n + 15) / 16) {
@@ -176,7 +164,7 @@ template <int V> int blk_rows_b(int64_t n)
 
 int batch_panel_rows(int64_t n, int dtype, int v)
 {
-    if (dtype == F32) return reg_panel_rows_variant(n, dtype, v);
+    (void)dtype;
     return v == 1 ? blk_rows_b<1>(n) : (v == 2 ? blk_rows_b<2>(n) : blk_rows_b<0>(n));
 }
 
@@ -185,72 +173,43 @@ int batch_panel_rows(int64_t n, int dtype, int v)
 bool variant_ok(int64_t n, int dtype, int v)
 {
     if (v < 0 || v > 2) return false;
-    if (v > 0 && batch_panel_rows(n, dtype, v) == batch_panel_rows(n, dtype, 0) &&
-        dtype == F64)
-        return false;
+    if (v > 0 && batch_panel_rows(n, dtype, v) == batch_panel_rows(n, dtype, 0)) return false;
     return batch_panel_rows(n, dtype, v) >= 3 * n;
 }
 
-template <int NCT, int V>
+
+// ---- launch dispatch on the width class and variant ----------------------------------------
+template <typename T, int NCT, int V>
 hipError_t factor_blk_batched_cv(const FactorTask *tasks, int nt, int64_t blocks,
                                  const void *const *A, char *ws, hipStream_t st)
 {
     using C = BlkShapeB<NCT, V>;
-    hipLaunchKernelGGL((k_factor_blk_batched<NCT, V>), dim3((unsigned)blocks), dim3(C::NW * 64),
-                       C::LDS, st, tasks, nt, A, ws);
+    hipLaunchKernelGGL((k_factor_blk_batched<T, NCT, V>), dim3((unsigned)blocks),
+                       dim3(C::NW * 64), C::template lds<T>(), st, tasks, nt, A, ws);
     return hipGetLastError();
 }
 
-template <int NCT>
+template <typename T, int NCT>
 hipError_t factor_blk_batched_c(int v, const FactorTask *tasks, int nt, int64_t blocks,
                                 const void *const *A, char *ws, hipStream_t st)
 {
-    if (v == 1) return factor_blk_batched_cv<NCT, 1>(tasks, nt, blocks, A, ws, st);
-    if (v == 2) return factor_blk_batched_cv<NCT, 2>(tasks, nt, blocks, A, ws, st);
-    return factor_blk_batched_cv<NCT, 0>(tasks, nt, blocks, A, ws, st);
+    // only the variants that exist (variant_ok) are instantiated
+    if constexpr (NCT < 4)
+        if (v == 1) return factor_blk_batched_cv<T, NCT, 1>(tasks, nt, blocks, A, ws, st);
+    if constexpr (NCT == 1)
+        if (v == 2) return factor_blk_batched_cv<T, NCT, 2>(tasks, nt, blocks, A, ws, st);
+    return factor_blk_batched_cv<T, NCT, 0>(tasks, nt, blocks, A, ws, st);
 }
 
+template <typename T>
 hipError_t factor_blk_batched(int64_t n, int v, const FactorTask *tasks, int nt, int64_t blocks,
                               const void *const *A, char *ws, hipStream_t st)
 {
     switch ((n + 15) / 16) {
-    case 1: return factor_blk_batched_c<1>(v, tasks, nt, blocks, A, ws, st);
-    case 2: return factor_blk_batched_c<2>(v, tasks, nt, blocks, A, ws, st);
-    case 3: return factor_blk_batched_c<3>(v, tasks, nt, blocks, A, ws, st);
-    default: return factor_blk_batched_c<4>(v, tasks, nt, blocks, A, ws, st);
-    }
-}
-
-// ---- launch dispatch on the width class and variant ----------------------------------------
-template <typename Tin, typename T, int NC, int V>
-hipError_t factor_batched_cv(const FactorTask *tasks, int nt, int64_t blocks, const void *const *A,
-                             char *ws, hipStream_t st)
-{
-    using C = regpanel::RegCfg<T, NC, 1, V>;
-    hipLaunchKernelGGL((k_factor_batched<Tin, T, NC, C::RW, C::NW>), dim3((unsigned)blocks),
-                       dim3(C::NW * 64), 0, st, tasks, nt, A, ws);
-    return hipGetLastError();
-}
-
-template <typename Tin, typename T, int NC>
-hipError_t factor_batched_c(int v, const FactorTask *tasks, int nt, int64_t blocks,
-                            const void *const *A, char *ws, hipStream_t st)
-{
-    if (v == 1) return factor_batched_cv<Tin, T, NC, 1>(tasks, nt, blocks, A, ws, st);
-    if (v == 2) return factor_batched_cv<Tin, T, NC, 2>(tasks, nt, blocks, A, ws, st);
-    return factor_batched_cv<Tin, T, NC, 0>(tasks, nt, blocks, A, ws, st);
-}
-
-template <typename Tin, typename T>
-hipError_t factor_batched(int64_t n, int v, const FactorTask *tasks, int nt, int64_t blocks,
-                          const void *const *A, char *ws, hipStream_t st)
-{
-    switch (width_class(n)) {
-    case 0: return factor_batched_c<Tin, T, 4>(v, tasks, nt, blocks, A, ws, st);
-    case 1: return factor_batched_c<Tin, T, 8>(v, tasks, nt, blocks, A, ws, st);
-    case 2: return factor_batched_c<Tin, T, 16>(v, tasks, nt, blocks, A, ws, st);
-    case 3: return factor_batched_c<Tin, T, 32>(v, tasks, nt, blocks, A, ws, st);
-    default: return factor_batched_c<Tin, T, 64>(v, tasks, nt, blocks, A, ws, st);
+    case 1: return factor_blk_batched_c<T, 1>(v, tasks, nt, blocks, A, ws, st);
+    case 2: return factor_blk_batched_c<T, 2>(v, tasks, nt, blocks, A, ws, st);
+    case 3: return factor_blk_batched_c<T, 3>(v, tasks, nt, blocks, A, ws, st);
+    default: return factor_blk_batched_c<T, 4>(v, tasks, nt, blocks, A, ws, st);
     }
 }
 
@@ -566,11 +525,11 @@ tsqr_status tsqr_qr_batched(tsqr_batch_plan plan, const void *const *d_A, void *
             ProfScope ps(la.level == 0 ? PC_FACTOR0 : PC_FACTOR_TREE, st);
             const FactorTask *t = (const FactorTask *)tab;
             if (la.level == 0 && f32)
-                TSQR_HIP_CHECK((factor_batched<float, float>(la.n, la.variant, t, la.ntasks,
-                                                             la.blocks, d_A, w, st)));
+                TSQR_HIP_CHECK((factor_blk_batched<float>(la.n, la.variant, t, la.ntasks,
+                                                          la.blocks, d_A, w, st)));
             else
-                TSQR_HIP_CHECK((factor_blk_batched(la.n, la.variant, t, la.ntasks,
-                                                               la.blocks, d_A, w, st)));
+                TSQR_HIP_CHECK((factor_blk_batched<double>(la.n, la.variant, t, la.ntasks,
+                                                           la.blocks, d_A, w, st)));
         } else if (la.kind == LK_FINAL) {
             ProfScope ps(PC_FINALIZE, st);
             const FinalTask *t = (const FinalTask *)tab;

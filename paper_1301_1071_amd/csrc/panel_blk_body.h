@@ -31,41 +31,80 @@ namespace tsqr {
 namespace blkpanel {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ d4_t mfma4(double a, double b, d4_t c)
-{
-    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
-}
-
-// value of lane KK of this lane's 16-lane row (DPP row_newbcast)
-template <int KK> __device__ __forceinline__ double bcast16(double v)
-{
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + KK, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + KK, 0xf, 0xf, false);
-    return __hiloint2double(hi, lo);
-}
-
-// v[l] + v[l ^ 16] and v[l] + v[l ^ 32] through the gfx950 lane-swap instructions (the two
-// partners end up in the two outputs, so each pair of lanes forms the same sum)
-__device__ __forceinline__ double sum_xor16(double v)
-{
-    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-__device__ __forceinline__ double sum_xor32(double v)
-{
-    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
-    return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
-}
-
-__device__ __forceinline__ double rcp_refined(double x)
-{
-    double r = __builtin_amdgcn_rcp(x);
-    r = fma(r, fma(-x, r, 1.0), r);
-    return fma(r, fma(-x, r, 1.0), r);
-}
+// Element-type specifics of the 16x16x4 matrix-core tiles.  The A and B operand layouts are
+// the same for FP64 and FP32 (lane l: A[l % 16][l / 16], B[l / 16][l % 16]); the accumulator
+// holds row rit(l / 16, i) of column l % 16 in value i, with rit = l/16 + 4i (FP64) or
+// 4 (l/16) + i (FP32).
+template <typename T> struct BlkT;
+template <> struct BlkT<double> {
+    typedef d4_t acc_t;
+    static __device__ __forceinline__ acc_t mfma(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static constexpr __host__ __device__ int rit(int lr, int i) { return lr + 4 * i; }
+    static constexpr __host__ __device__ int kk_lr(int kk) { return kk & 3; }
+    static constexpr __host__ __device__ int kk_i(int kk) { return kk >> 2; }
+    // value of lane KK of this lane's 16-lane row (DPP row_newbcast)
+    template <int KK> static __device__ __forceinline__ double bcast16(double v)
+    {
+        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + KK, 0xf, 0xf, false);
+        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + KK, 0xf, 0xf, false);
+        return __hiloint2double(hi, lo);
+    }
+    // v[l] + v[l ^ 16] and v[l] + v[l ^ 32] through the gfx950 lane-swap instructions (the two
+    // partners end up in the two outputs, so each pair of lanes forms the same sum)
+    static __device__ __forceinline__ double sum_xor16(double v)
+    {
+        const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+        const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+        return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+    }
+    static __device__ __forceinline__ double sum_xor32(double v)
+    {
+        const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+        const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+        return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+    }
+    // reciprocal: hardware estimate and two Newton steps
+    static __device__ __forceinline__ double rcp(double x)
+    {
+        double r = __builtin_amdgcn_rcp(x);
+        r = fma(r, fma(-x, r, 1.0), r);
+        return fma(r, fma(-x, r, 1.0), r);
+    }
+};
+template <> struct BlkT<float> {
+    typedef f4_t acc_t;
+    static __device__ __forceinline__ acc_t mfma(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static constexpr __host__ __device__ int rit(int lr, int i) { return 4 * lr + i; }
+    static constexpr __host__ __device__ int kk_lr(int kk) { return kk >> 2; }
+    static constexpr __host__ __device__ int kk_i(int kk) { return kk & 3; }
+    template <int KK> static __device__ __forceinline__ float bcast16(float v)
+    {
+        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + KK, 0xf, 0xf, false));
+    }
+    static __device__ __forceinline__ float sum_xor16(float v)
+    {
+        const auto x = __builtin_amdgcn_permlane16_swap(__float_as_int(v), __float_as_int(v), false, false);
+        return __int_as_float(x[0]) + __int_as_float(x[1]);
+    }
+    static __device__ __forceinline__ float sum_xor32(float v)
+    {
+        const auto x = __builtin_amdgcn_permlane32_swap(__float_as_int(v), __float_as_int(v), false, false);
+        return __int_as_float(x[0]) + __int_as_float(x[1]);
+    }
+    static __device__ __forceinline__ float rcp(float x)
+    {
+        float r = __builtin_amdgcn_rcpf(x);
+        return fmaf(r, fmaf(-x, r, 1.0f), r);
+    }
+};
 
 template <int I, int N, typename F> __device__ __forceinline__ void static_for(F &&f)
 {
@@ -77,28 +116,30 @@ template <int I, int N, typename F> __device__ __forceinline__ void static_for(F
 
 // LDS of one work-group (dynamic: more than 64 KiB for the widest panels).  TC = column tiles
 // whose per-wave products are reduced at a time.
-template <int NCT, int RT, int NW, int TC> struct BlkSmem {
-    double part[2][NW][16];          // per-step partial dots of the block's columns
-    double rowk[2][16];              // pivot row k restricted to the block
-    double tau[NCT * 16], u[NCT * 16], beta[NCT * 16];
+template <typename T, int NCT, int RT, int NW, int TC> struct BlkSmem {
+    T part[2][NW][16];               // per-step partial dots of the block's columns
+    T rowk[2][16];                   // pivot row k restricted to the block
+    T tau[NCT * 16], u[NCT * 16], beta[NCT * 16];
     union {
-        double red[NW][TC][256];     // per-wave partial products (G, W) before the wave sum
-        double vt[NW][16][17];       // one row tile of V per wave, row-major (A operand of V Y)
+        T red[NW][TC][256];          // per-wave partial products (G, W) before the wave sum
+        T vt[NW][16][17];            // one row tile of V per wave, row-major (A operand of V Y)
     };
-    double wsum[NCT][256];           // summed products: slot kt = G = V^T V, slot t = W of tile t
-    double tstore[NCT][16][17];      // T of every block (kept for the Q1 formation)
-    double ybuf[16][NCT * 16 + 1];   // Y = T^T W (or T W) for the trailing tiles
+    T wsum[NCT][256];                // summed products: slot kt = G = V^T V, slot t = W of tile t
+    T tstore[NCT][16][17];           // T of every block (kept for the Q1 formation)
+    T ybuf[16][NCT * 16 + 1];        // Y = T^T W (or T W) for the trailing tiles
 };
 
-template <int NCT, int RT, int NW, int TC>
-__device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const double *__restrict__ X,
-                                                 int64_t ldx, double *__restrict__ q1,
+template <typename Tin, typename T, int NCT, int RT, int NW, int TC>
+__device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin *__restrict__ X,
+                                                 int64_t ldx, T *__restrict__ q1,
                                                  double *__restrict__ S, int64_t p)
 {
+    using K = BlkT<T>;
+    typedef typename K::acc_t acc_t;
     constexpr int B = NW * RT * 16;
     constexpr int NT = NW * 64;
     extern __shared__ __align__(16) unsigned char blk_smem_raw[];
-    BlkSmem<NCT, RT, NW, TC> &sm = *reinterpret_cast<BlkSmem<NCT, RT, NW, TC> *>(blk_smem_raw);
+    BlkSmem<T, NCT, RT, NW, TC> &sm = *reinterpret_cast<BlkSmem<T, NCT, RT, NW, TC> *>(blk_smem_raw);
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -108,10 +149,10 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
     const int nrow = (int)min((int64_t)B, rows - prow0);
     // row tiles are dealt out to the waves in turn (tile g belongs to wave g % NW), so the
     // finished top rows and the pivot tile of every block are spread over the waves
-    auto row_of = [&](int rt, int i) { return 16 * (rt * NW + w) + lr + 4 * i; };
+    auto row_of = [&](int rt, int i) { return 16 * (rt * NW + w) + K::rit(lr, i); };
 
     // ---- load the panel (zero rows past the end and columns past n) -------------------------
-    d4_t P[RT][NCT];
+    acc_t P[RT][NCT];
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -119,23 +160,23 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = row_of(rt, i), c = 16 * ct + lc;
-                P[rt][ct][i] = (r < nrow && c < n) ? X[(prow0 + r) * ldx + c] : 0.0;
+                P[rt][ct][i] = (r < nrow && c < n) ? (T)X[(prow0 + r) * ldx + c] : T(0);
             }
 
     // V of block KT from the stored x's: unit diagonal, zero above, x / (alpha - beta) below;
     // zero for a skipped reflector (tau = 0) or a padding column
-    auto gather_v = [&](auto KT, double (&V)[RT][4]) {
+    auto gather_v = [&](auto KT, T (&V)[RT][4]) {
         constexpr int kt = decltype(KT)::value;
         const int c = 16 * kt + lc;
-        const double tc = (c < n) ? sm.tau[c] : 0.0;
-        const double inv = (tc != 0.0) ? rcp_refined(sm.u[c]) : 0.0;
+        const T tc = (c < n) ? sm.tau[c] : T(0);
+        const T inv = (tc != T(0)) ? K::rcp(sm.u[c]) : T(0);
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int r = row_of(rt, i);
-                double v = 0.0;
-                if (tc != 0.0) v = (r > c) ? P[rt][kt][i] * inv : ((r == c) ? 1.0 : 0.0);
+                T v = T(0);
+                if (tc != T(0)) v = (r > c) ? P[rt][kt][i] * inv : ((r == c) ? T(1) : T(0));
                 V[rt][i] = v;
             }
     };
@@ -143,7 +184,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
     // W_t = V^T A[:, tile t] for tiles t >= T0 into wsum[t], and with WITH_G also G = V^T V into
     // wsum[KT] (then T0 > KT); summed over the waves in a fixed order, TC products at a time.
     // Ends with a barrier.
-    auto block_products = [&](auto KT, auto T0, auto WITH_G, const double (&V)[RT][4]) {
+    auto block_products = [&](auto KT, auto T0, auto WITH_G, const T (&V)[RT][4]) {
         constexpr int kt = decltype(KT)::value, t0 = decltype(T0)::value;
         constexpr bool with_g = decltype(WITH_G)::value;
         constexpr int L = (with_g ? 1 : 0) + (NCT - t0);          // products: [G,] tiles t0..
@@ -151,9 +192,9 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         static_for<0, NCH>([&](auto CH) {
             constexpr int c0 = decltype(CH)::value * TC;
             // product e of the list: G for e == 0 with_g, else tile t0 + e - with_g
-            d4_t acc[TC];
+            acc_t acc[TC];
 #pragma unroll
-            for (int s = 0; s < TC; ++s) acc[s] = d4_t{0, 0, 0, 0};
+            for (int s = 0; s < TC; ++s) acc[s] = acc_t{0, 0, 0, 0};
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
@@ -162,20 +203,20 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
                     for (int s = 0; s < TC; ++s) {
                         const int e = c0 + s;
                         if (e >= L) continue;
-                        if (with_g && e == 0) acc[s] = mfma4(V[rt][i], V[rt][i], acc[s]);
-                        else acc[s] = mfma4(V[rt][i], P[rt][t0 + e - (with_g ? 1 : 0)][i], acc[s]);
+                        if (with_g && e == 0) acc[s] = K::mfma(V[rt][i], V[rt][i], acc[s]);
+                        else acc[s] = K::mfma(V[rt][i], P[rt][t0 + e - (with_g ? 1 : 0)][i], acc[s]);
                     }
 #pragma unroll
             for (int s = 0; s < TC; ++s)
                 if (c0 + s < L)
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) sm.red[w][s][(lr + 4 * i) * 16 + lc] = acc[s][i];
+                    for (int i = 0; i < 4; ++i) sm.red[w][s][K::rit(lr, i) * 16 + lc] = acc[s][i];
             __syncthreads();
             for (int e2 = tid; e2 < TC * 256; e2 += NT) {
                 const int s = e2 >> 8, e = c0 + s;
                 if (e >= L) continue;
                 const int slot = (with_g && e == 0) ? kt : t0 + e - (with_g ? 1 : 0);
-                double sum = 0.0;
+                T sum = T(0);
 #pragma unroll
                 for (int ww = 0; ww < NW; ++ww) sum += sm.red[ww][s][e2 & 255];
                 sm.wsum[slot][e2 & 255] = sum;
@@ -192,16 +233,16 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         constexpr int kt = decltype(KT)::value;
         if (w == 0 && lane < 16) {
             const int i = lane;
-            double *trow = sm.tstore[kt][i];
+            T *trow = sm.tstore[kt][i];
             for (int j = 0; j < 16; ++j) {
                 const int cj = 16 * kt + j;
-                const double tj = (cj < n) ? sm.tau[cj] : 0.0;
-                double s0 = 0.0, s1 = 0.0;
+                const T tj = (cj < n) ? sm.tau[cj] : T(0);
+                T s0 = T(0), s1 = T(0);
                 for (int l = i; l < j; l += 2) {
                     s0 = fma(trow[l], sm.wsum[kt][l * 16 + j], s0);
                     if (l + 1 < j) s1 = fma(trow[l + 1], sm.wsum[kt][(l + 1) * 16 + j], s1);
                 }
-                trow[j] = (i < j) ? -tj * (s0 + s1) : ((i == j) ? tj : 0.0);
+                trow[j] = (i < j) ? -tj * (s0 + s1) : ((i == j) ? tj : T(0));
             }
         }
         __syncthreads();
@@ -213,34 +254,34 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         constexpr int kt = decltype(KT)::value, t0 = decltype(T0)::value;
         constexpr bool trans = decltype(TRANS)::value;
         for (int t = t0 + w; t < NCT; t += NW) {
-            d4_t acc = d4_t{0, 0, 0, 0};
+            acc_t acc = acc_t{0, 0, 0, 0};
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double a = trans ? sm.tstore[kt][4 * q + lr][lc] : sm.tstore[kt][lc][4 * q + lr];
-                const double b = sm.wsum[t][(4 * q + lr) * 16 + lc];
-                acc = mfma4(a, b, acc);
+                const T a = trans ? sm.tstore[kt][4 * q + lr][lc] : sm.tstore[kt][lc][4 * q + lr];
+                const T b = sm.wsum[t][(4 * q + lr) * 16 + lc];
+                acc = K::mfma(a, b, acc);
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sm.ybuf[lr + 4 * i][16 * t + lc] = acc[i];
+            for (int i = 0; i < 4; ++i) sm.ybuf[K::rit(lr, i)][16 * t + lc] = acc[i];
         }
         __syncthreads();
     };
 
     // A[:, tiles t >= T0] -= V * Y[:, tiles], Y in sm.ybuf; V re-laid out row tile by row tile
     // through this wave's sm.vt as the row-major A operand
-    auto block_update = [&](auto T0, const double (&V)[RT][4]) {
+    auto block_update = [&](auto T0, const T (&V)[RT][4]) {
         constexpr int t0 = decltype(T0)::value;
 #pragma unroll
         for (int rt = 0; rt < RT; ++rt) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) sm.vt[w][lr + 4 * i][lc] = V[rt][i];
+            for (int i = 0; i < 4; ++i) sm.vt[w][K::rit(lr, i)][lc] = V[rt][i];
             // (the wave reads back what its own lanes wrote: LDS operations of a wave are ordered)
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
-                const double a = sm.vt[w][lc][4 * q + lr];
+                const T a = sm.vt[w][lc][4 * q + lr];
 #pragma unroll
                 for (int t = t0; t < NCT; ++t)
-                    P[rt][t] = mfma4(a, -sm.ybuf[4 * q + lr][16 * t + lc], P[rt][t]);
+                    P[rt][t] = K::mfma(a, -sm.ybuf[4 * q + lr][16 * t + lc], P[rt][t]);
             }
         }
     };
@@ -250,63 +291,63 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         constexpr int kt = decltype(KT)::value;
         if (16 * kt >= n) return;
         // the 16 Householder steps of the block, unrolled: row k = 16 kt + kk lives in row tile
-        // kt, i.e. in wave kt % NW, tile slot kt / NW, value kk / 4 of the lanes with lr = kk % 4
+        // kt, i.e. in wave kt % NW, tile slot kt / NW, at row kk of that tile
         static_for<0, 16>([&](auto KK) {
             constexpr int kk = decltype(KK)::value;
             constexpr int par = kk & 1;
-            constexpr int rtk = kt / NW, ik = kk >> 2;
+            constexpr int rtk = kt / NW, ik = K::kk_i(kk);
             const int k = 16 * kt + kk;
             if (k >= n) return;
             const bool own = (w == kt % NW);                  // this wave holds row tile kt
-            if (own && lr == (kk & 3)) sm.rowk[par][lc] = P[rtk][kt][ik];
+            if (own && lr == K::kk_lr(kk)) sm.rowk[par][lc] = P[rtk][kt][ik];
             // pivot column x (rows > k) and the partial dots with the block's columns; tiles
             // above tile kt hold finished rows (x = 0, no update)
-            double xm[RT][4];
-            double d0 = 0.0, d1 = 0.0;
+            T xm[RT][4];
+            T d0 = T(0), d1 = T(0);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 const int gt = rt * NW + w;
                 if (gt > kt) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        xm[rt][i] = bcast16<kk>(P[rt][kt][i]);
+                        xm[rt][i] = K::template bcast16<kk>(P[rt][kt][i]);
                         if (i & 1) d1 = fma(xm[rt][i], P[rt][kt][i], d1);
                         else d0 = fma(xm[rt][i], P[rt][kt][i], d0);
                     }
                 } else if (gt == kt) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const double xv = bcast16<kk>(P[rt][kt][i]);
-                        xm[rt][i] = (lr + 4 * i > kk) ? xv : 0.0;
+                        const T xv = K::template bcast16<kk>(P[rt][kt][i]);
+                        xm[rt][i] = (K::rit(lr, i) > kk) ? xv : T(0);
                         if (i & 1) d1 = fma(xm[rt][i], P[rt][kt][i], d1);
                         else d0 = fma(xm[rt][i], P[rt][kt][i], d0);
                     }
                 } else {
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) xm[rt][i] = 0.0;
+                    for (int i = 0; i < 4; ++i) xm[rt][i] = T(0);
                 }
             }
-            const double d = sum_xor32(sum_xor16(d0 + d1));
+            const T d = K::sum_xor32(K::sum_xor16(d0 + d1));
             if (lr == 0) sm.part[par][w][lc] = d;
             __syncthreads();
-            double s2 = 0.0, pc = 0.0;
+            T s2 = T(0), pc = T(0);
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
                 s2 += sm.part[par][ww][kk];
                 pc += sm.part[par][ww][lc];
             }
-            const double alpha = sm.rowk[par][kk];
-            double tau = 0.0, u = 0.0, beta = alpha;
-            if (s2 != 0.0) {
-                const double nrm = sqrt(alpha * alpha + s2);
-                beta = (alpha >= 0.0) ? -nrm : nrm;
-                tau = 1.0 - alpha * rcp_refined(beta);
+            const T alpha = sm.rowk[par][kk];
+            T tau = T(0), u = T(0), beta = alpha;
+            if (s2 != T(0)) {
+                const T nrm = sqrt(alpha * alpha + s2);
+                beta = (alpha >= T(0)) ? -nrm : nrm;
+                tau = T(1) - alpha * K::rcp(beta);
                 u = alpha - beta;
             }
             if (tid == 0) { sm.tau[k] = tau; sm.u[k] = u; sm.beta[k] = beta; }
-            double coef = 0.0;
-            if (tau != 0.0 && lc > kk && 16 * kt + lc < n) {
-                const double inv = rcp_refined(u);
+            T coef = T(0);
+            if (tau != T(0) && lc > kk && 16 * kt + lc < n) {
+                const T inv = K::rcp(u);
                 coef = tau * (sm.rowk[par][lc] + inv * pc) * inv;
             }
 #pragma unroll
@@ -318,7 +359,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
                 } else if (gt == kt) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
-                        const double x = (lr + 4 * i == kk) ? u : xm[rt][i];
+                        const T x = (K::rit(lr, i) == kk) ? u : xm[rt][i];
                         P[rt][kt][i] = fma(-coef, x, P[rt][kt][i]);
                     }
                 }
@@ -327,7 +368,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         __syncthreads();      // tau, u of the block visible to every wave
         if constexpr (kt + 1 < NCT) {
             if (16 * (kt + 1) < n) {
-                double V[RT][4];
+                T V[RT][4];
                 gather_v(KT, V);
                 block_products(KT, std::integral_constant<int, kt + 1>{}, std::true_type{}, V);
                 block_t(KT);
@@ -347,7 +388,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
             for (int i = 0; i < 4; ++i) {
                 const int r = row_of(rt, i), c = 16 * ct + lc;
                 if (r < n && c < n)
-                    S[(p * n + r) * n + c] = (c > r) ? P[rt][ct][i] : ((c == r) ? sm.beta[r] : 0.0);
+                    S[(p * n + r) * n + c] = (c > r) ? (double)P[rt][ct][i] : ((c == r) ? (double)sm.beta[r] : T(0) /*keep*/);
             }
     if (q1 == nullptr) return;
 
@@ -357,7 +398,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         constexpr int kt = NCT - 1 - decltype(I)::value;
         if (kt >= nblk) return;
         using KT = std::integral_constant<int, kt>;
-        double V[RT][4];
+        T V[RT][4];
         gather_v(KT{}, V);
         if (kt == nblk - 1) {
             // the last block's T (its trailing step did not run)
@@ -369,7 +410,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const doub
         for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
             for (int i = 0; i < 4; ++i)
-                P[rt][kt][i] = (row_of(rt, i) == 16 * kt + lc) ? 1.0 : 0.0;
+                P[rt][kt][i] = (row_of(rt, i) == 16 * kt + lc) ? T(1) : T(0);
         block_products(KT{}, KT{}, std::false_type{}, V);
         block_y(KT{}, KT{}, std::false_type{});
         block_update(KT{}, V);

@@ -1,0 +1,52 @@
+// Shapes, kernel and launcher of the blocked panel kernel for the single-matrix path (device
+// body in panel_blk_body.h); included by panel_blk.hip and the per-width panel_blk_wide*.hip.
+#pragma once
+
+#include "panel_blk_body.h"
+
+namespace tsqr {
+namespace blklaunch {
+
+using blkpanel::BlkSmem;
+
+// Panel shapes (no register spills; two work-groups per CU up to n = 64): 4 waves with 256
+// rows for 32 < n <= 64 and 384 rows for n <= 32; 8 waves with 256 rows for 64 < n <= 128
+// (one work-group per CU).  FP32 uses the same shapes.
+template <typename T, int NCT> struct BlkShape {
+    static constexpr int NW = (NCT <= 4) ? 4 : 8;
+    static constexpr int RT = (NCT <= 2) ? 6 : ((NCT <= 4) ? 4 : 2);
+    static constexpr int TC = (NCT <= 4) ? NCT : 2;
+    static constexpr int B = NW * RT * 16;
+    static constexpr size_t LDS = sizeof(BlkSmem<T, NCT, RT, NW, TC>);
+};
+
+template <typename Tin, typename T, int NCT>
+__global__ void __launch_bounds__((NCT <= 4) ? 256 : 512, (NCT <= 4) ? 2 : 1)
+k_factor_blk(int64_t rows, int n, const Tin *__restrict__ X, int64_t ldx, T *__restrict__ q1,
+             double *__restrict__ S)
+{
+    using C = BlkShape<T, NCT>;
+    blkpanel::factor_blk_panel<Tin, T, NCT, C::RT, C::NW, C::TC>(rows, n, X, ldx, q1, S,
+                                                                blockIdx.x);
+}
+
+template <typename Tin, typename T, int NCT>
+hipError_t factor_blk_launch(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
+                             double *S, hipStream_t st)
+{
+    using C = BlkShape<T, NCT>;
+    const int64_t panels = ceil_div(rows, C::B);
+    static bool attr_set = false;
+    if (C::LDS > 64 * 1024 && !attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void *)k_factor_blk<Tin, T, NCT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((k_factor_blk<Tin, T, NCT>), dim3((unsigned)panels), dim3(C::NW * 64),
+                       C::LDS, st, rows, (int)n, (const Tin *)X, ldx, (T *)q1, S);
+    return hipGetLastError();
+}
+
+}  // namespace blklaunch
+}  // namespace tsqr

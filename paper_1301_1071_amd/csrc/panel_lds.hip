@@ -3,8 +3,8 @@
 // Step 1 of direct TSQR (Sec. III-B): one work-group factors one row panel A_p = Q1_p R_p with
 // Householder reflections (Sec. III-A), writes R_p into the stacked-R buffer (block p = rows
 // [p n, p n + n), the ordering the step-2 reduce task relies on) and, when Q is wanted, forms
-// Q1_p = H_1 ... H_n [I; 0] explicitly so that step 3 is a plain product Q1_p * Q2_p.
-// Step 3 (and every level of the recursive tree of Sec. III-C): out_p = Q1_p * W_p.
+// Q1_p = H_1 ... H_n [I; 0] explicitly so that step 3 is a plain product Q1_p * Q2_p.  Used for
+// explicitly requested panel heights (tsqr_opts.panel_rows) and short FP32 stacks.
 //
 // Householder convention: for column k, x = A[k:, k], alpha = x_0, s2 = ||x_{1:}||^2;
 // beta = -sign(alpha) sqrt(alpha^2 + s2) (sign(0) = +1), tau = (beta - alpha) / beta and
@@ -159,35 +159,6 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
     }
 }
 
-// out rows of panel p = Q1_p (b x n) * W_p (n x k); each lane owns one output column.
-template <typename Tq, typename To, int NPM>
-__global__ void __launch_bounds__(kThreads)
-k_apply_rows(int64_t rows, int n, int b, const Tq *__restrict__ q1, const double *__restrict__ W,
-             int64_t ldw, int64_t wstride, int k, To *__restrict__ out0, int64_t ld0, int k0,
-             To *__restrict__ out1, int64_t ld1)
-{
-    const int lane = threadIdx.x & 63;
-    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t p = blockIdx.x;
-    const int j = blockIdx.y * 64 + lane;
-    const double *Wp = W + p * wstride * ldw;
-    Tq wr[NPM];
-#pragma unroll
-    for (int c = 0; c < NPM; ++c) wr[c] = (c < n && j < k) ? (Tq)Wp[(int64_t)c * ldw + j] : Tq(0);
-    const int64_t rb = p * (int64_t)b;
-    const int64_t re = min(rows, rb + b);
-    for (int64_t r = rb + w; r < re; r += 4) {
-        const Tq *qr = q1 + r * n;
-        Tq acc = Tq(0);
-#pragma unroll
-        for (int c = 0; c < NPM; ++c) {
-            if (c < n) acc = fma(qr[c], wr[c], acc);
-        }
-        if (j < k0) out0[r * ld0 + j] = (To)acc;
-        else if (j < k) out1[r * ld1 + (j - k0)] = (To)acc;
-    }
-}
-
 template <typename T>
 size_t lds_bytes(int n, int b) { return sizeof(T) * (size_t)n * (b + 1); }
 
@@ -214,25 +185,6 @@ hipError_t factor_impl(int64_t rows, int64_t n, int b, const void *X, int64_t ld
     const int64_t panels = ceil_div(rows, b);
     hipLaunchKernelGGL(kern, dim3((unsigned)panels), dim3(kThreads), lds, st, rows, (int)n, b,
                        b + 1, nc_log2_for(n), (const Tin *)X, ldx, (T *)q1, S, (T *)gpanel);
-    return hipGetLastError();
-}
-
-template <typename Tq, typename To>
-hipError_t apply_impl(int64_t rows, int64_t n, int b, const void *q1, const double *W,
-                      int64_t ldw, int64_t wstride, int k, void *out0, int64_t ld0, int k0,
-                      void *out1, int64_t ld1, hipStream_t st)
-{
-    const int64_t panels = ceil_div(rows, b);
-    dim3 grid((unsigned)panels, (unsigned)ceil_div(k, 64));
-#define TSQR_APPLY_CASE(NPM)                                                                 \
-    hipLaunchKernelGGL((k_apply_rows<Tq, To, NPM>), grid, dim3(kThreads), 0, st, rows, (int)n, \
-                       b, (const Tq *)q1, W, ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1,  \
-                       ld1)
-    if (n <= 16) TSQR_APPLY_CASE(16);
-    else if (n <= 32) TSQR_APPLY_CASE(32);
-    else if (n <= 64) TSQR_APPLY_CASE(64);
-    else TSQR_APPLY_CASE(128);
-#undef TSQR_APPLY_CASE
     return hipGetLastError();
 }
 
@@ -265,24 +217,6 @@ hipError_t launch_factor(int in_dtype, int dtype, int64_t rows, int64_t n, int b
     }
     if (in_dtype == F64) return factor_impl<double, float>(rows, n, b, X, ldx, q1, S, gpanel, st);
     return factor_impl<float, float>(rows, n, b, X, ldx, q1, S, gpanel, st);
-}
-
-hipError_t launch_apply(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
-                        const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
-                        void *out0, int64_t ld0, int k0, void *out1, int64_t ld1, hipStream_t st)
-{
-    if (q_dtype == F64) {
-        if (out_dtype == F64)
-            return apply_impl<double, double>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0,
-                                              out1, ld1, st);
-        return apply_impl<double, float>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1,
-                                         ld1, st);
-    }
-    if (out_dtype == F64)
-        return apply_impl<float, double>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1,
-                                         ld1, st);
-    return apply_impl<float, float>(rows, n, b, q1, W, ldw, wstride, k, out0, ld0, k0, out1, ld1,
-                                    st);
 }
 
 }  // namespace tsqr

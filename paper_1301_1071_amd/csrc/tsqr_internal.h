@@ -89,26 +89,15 @@ hipError_t launch_factor(int in_dtype, int dtype, int64_t rows, int64_t n, int b
                          const void *X, int64_t ldx, void *q1, double *S, void *gpanel,
                          hipStream_t st);
 
-// out = Q1 * W per panel: panel p (rows [p b, p b + b)) uses W rows [p*wstride, p*wstride + n).
-// Columns [0, k0) of the product go to out0 (ld0), columns [k0, k) to out1 (ld1).
-hipError_t launch_apply(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
-                        const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
-                        void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
-                        hipStream_t st);
-
-// ---- launchers (panel_reg.hip): register-resident panels, the default for every level -------
-// Panel height of the register kernel for (n, dtype): 512/256/192/192 rows (FP64, n <= 16/32/
-// 64/128), twice that for FP32.
+// ---- launchers (panel_blk.hip): blocked register panels, the default for every level --------
+// Panel height of the blocked kernel for (n, dtype): 384 rows for n <= 32, 256 rows above.
 int reg_panel_rows(int64_t n, int dtype);
 hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, const void *X,
                              int64_t ldx, void *q1, double *S, hipStream_t st);
-// Same contract as launch_apply (any panel height b).
-hipError_t launch_apply_staged(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
-                               const void *q1, const double *W, int64_t ldw, int64_t wstride,
-                               int k, void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
-                               hipStream_t st);
 
-// ---- launchers (apply_mfma.hip): step 3 on the matrix cores (same contract as launch_apply) --
+// ---- launchers (apply_mfma.hip): step 3 on the matrix cores --------------------------------
+// out = Q1 * W per panel: panel p (rows [p b, p b + b)) uses W rows [p*wstride, p*wstride + n).
+// Columns [0, k0) of the product go to out0 (ld0), columns [k0, k) to out1 (ld1).
 hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                              const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
                              void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,

@@ -152,7 +152,7 @@ def test_svd_known_spectrum_ill_conditioned():
 
 
 # --------------------------------------------------------------------- FP32 path and refinement
-@pytest.mark.parametrize("m,n", [(100_000, 25), (30_000, 8), (9000, 64)])
+@pytest.mark.parametrize("m,n", [(100_000, 25), (30_000, 8), (9000, 64), (20_000, 100)])
 def test_qr_f32_io(m, n):
     t = tsqr_mod()
     A32 = gauss(m, n, 60 + n).astype(np.float32)
