@@ -15,49 +15,81 @@ namespace {
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
-constexpr int kGramMaxBlocks = 512;
-constexpr int kGramTiles = 8;     // n <= 128
+constexpr int kGramMaxBlocks = 1024;
+constexpr int kGramThreads = 256;
+// rows per staged chunk (the X and Y chunks stay within 36 KiB of LDS)
+template <int NP> constexpr int gram_rows() { return NP <= 64 ? 32 : 16; }
 
-// Partial Gram of one row block on the matrix cores: C_b = X_b^T Y_b.  Wave w owns the 16-column
-// strips mt = w, w+4, ... of X and all strips of Y; v_mfma_f64_16x16x4 contracts 4 rows at a time
-// with A = X^T (lane l: X[r + l/16][16 mt + l%16]) and B = Y (lane l: Y[r + l/16][16 nt + l%16]).
-__global__ void __launch_bounds__(256)
+// Partial Gram of one row range on the matrix cores: C_b = X_b^T Y_b.  Chunks of 32 (or 16) rows of X
+// and Y are loaded with coalesced reads one chunk ahead (registers), staged through LDS, and
+// every wave accumulates its share of the T x T output tiles (T = ceil(n/16)) with
+// v_mfma_f64_16x16x4 over the chunk: A = X^T (lane l: X[r + l/16][16 a + l%16]), B = Y (lane l:
+// Y[r + l/16][16 b + l%16]).
+template <int NP>
+__global__ void __launch_bounds__(kGramThreads)
 k_gram(int64_t m, int n, const double *__restrict__ X, int64_t ldx, const double *__restrict__ Y,
        int64_t ldy, int64_t rows_per_block, double *__restrict__ part)
 {
-    const int lane = threadIdx.x & 63;
-    const int w = threadIdx.x >> 6;
-    const int T = (n + 15) >> 4;
+    constexpr int kGramRows = gram_rows<NP>();
+    constexpr int T = NP / 16, NTILE = T * T, TPW = (NTILE + 3) / 4;   // tiles per wave
+    constexpr int LDS_LD = NP + 1;
+    constexpr int PER = kGramRows * NP / kGramThreads;                 // prefetched values
+    __shared__ double xs[kGramRows * LDS_LD], ys[kGramRows * LDS_LD];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int64_t r_begin = (int64_t)blockIdx.x * rows_per_block;
     const int64_t r_end = min(m, r_begin + rows_per_block);
-    const int cx = lane & 15, rq = lane >> 4;
-    double *out = part + (int64_t)blockIdx.x * n * n;
-    for (int mt = w; mt < T; mt += 4) {
-        d4_t acc[kGramTiles];
+    d4_t acc[TPW];
 #pragma unroll
-        for (int t = 0; t < kGramTiles; ++t) acc[t] = d4_t{0, 0, 0, 0};
-        const int ca = 16 * mt + cx;
-        for (int64_t r = r_begin; r < r_end; r += 4) {
-            const int64_t rr = r + rq;
-            const bool rin = rr < r_end;
-            const double a = (rin && ca < n) ? X[rr * ldx + ca] : 0.0;
+    for (int t = 0; t < TPW; ++t) acc[t] = d4_t{0, 0, 0, 0};
+    double px[PER], py[PER];
+    auto fetch = [&](int64_t r0) {
 #pragma unroll
-            for (int t = 0; t < kGramTiles; ++t) {
-                if (t < T) {
-                    const int cb = 16 * t + cx;
-                    const double b = (rin && cb < n) ? Y[rr * ldy + cb] : 0.0;
-                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[t], 0, 0, 0);
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * kGramThreads;
+            const int r = e / NP, c = e - r * NP;
+            const bool ok = (r0 + r < r_end) && c < n;
+            px[q] = ok ? X[(r0 + r) * ldx + c] : 0.0;
+            py[q] = ok ? Y[(r0 + r) * ldy + c] : 0.0;
+        }
+    };
+    if (r_begin < r_end) fetch(r_begin);
+    for (int64_t r0 = r_begin; r0 < r_end; r0 += kGramRows) {
+        __syncthreads();                       // previous chunk fully consumed
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            const int e = tid + q * kGramThreads;
+            const int r = e / NP, c = e - r * NP;
+            xs[r * LDS_LD + c] = px[q];
+            ys[r * LDS_LD + c] = py[q];
+        }
+        __syncthreads();
+        if (r0 + kGramRows < r_end) fetch(r0 + kGramRows);
+#pragma unroll
+        for (int k = 0; k < kGramRows / 4; ++k) {
+            const int r = 4 * k + (lane >> 4);
+#pragma unroll
+            for (int t = 0; t < TPW; ++t) {
+                const int tile = w * TPW + t;
+                if (tile < NTILE) {
+                    const int a = tile / T, b = tile - a * T;
+                    acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(xs[r * LDS_LD + 16 * a + (lane & 15)],
+                                                                  ys[r * LDS_LD + 16 * b + (lane & 15)],
+                                                                  acc[t], 0, 0, 0);
                 }
             }
         }
+    }
+    double *out = part + (int64_t)blockIdx.x * n * n;
 #pragma unroll
-        for (int t = 0; t < kGramTiles; ++t) {
-            if (t < T) {
+    for (int t = 0; t < TPW; ++t) {
+        const int tile = w * TPW + t;
+        if (tile < NTILE) {
+            const int a = tile / T, b = tile - a * T;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int row = 16 * mt + rq + 4 * i, col = 16 * t + cx;   // f64 result layout
-                    if (row < n && col < n) out[(int64_t)row * n + col] = acc[t][i];
-                }
+            for (int i = 0; i < 4; ++i) {
+                const int row = 16 * a + (lane >> 4) + 4 * i, col = 16 * b + (lane & 15);   // f64 layout
+                if (row < n && col < n) out[(int64_t)row * n + col] = acc[t][i];
             }
         }
     }
@@ -177,17 +209,24 @@ k_svd_bwd_small(int n, const double *__restrict__ S, const double *__restrict__ 
 
 int gram_blocks(int64_t m)
 {
-    int64_t b = ceil_div(m, 2048);
+    int64_t b = ceil_div(m, 4096);
     return (int)(b < 1 ? 1 : (b > kGramMaxBlocks ? kGramMaxBlocks : b));
 }
 
 hipError_t launch_gram(int64_t m, int64_t n, const double *X, int64_t ldx, const double *Y,
                        int64_t ldy, double *part, double *G, hipStream_t st)
 {
-    if (n > 16 * kGramTiles) return hipErrorInvalidValue;
     const int nb = gram_blocks(m);
-    const int64_t rpb = (ceil_div(m, nb) + 3) / 4 * 4;
-    hipLaunchKernelGGL(k_gram, dim3(nb), dim3(256), 0, st, m, (int)n, X, ldx, Y, ldy, rpb, part);
+    const int64_t rpb = ceil_div(ceil_div(m, nb), 32) * 32;
+#define TSQR_GRAM(NP)                                                                          \
+    hipLaunchKernelGGL(k_gram<NP>, dim3(nb), dim3(kGramThreads), 0, st, m, (int)n, X, ldx, Y,  \
+                       ldy, rpb, part)
+    if (n <= 16) TSQR_GRAM(16);
+    else if (n <= 32) TSQR_GRAM(32);
+    else if (n <= 64) TSQR_GRAM(64);
+    else if (n <= 128) TSQR_GRAM(128);
+    else return hipErrorInvalidValue;
+#undef TSQR_GRAM
     const int64_t nn = n * n;
     hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, st, nn, part,
                        nb, G);

@@ -4,96 +4,50 @@
 // restores orthogonality but cannot lift the backward error ||A - QR|| above the FP32 level, so
 // the pass below refines against A itself (preconditioned Cholesky QR, Yamazaki, Tomov & Dongarra
 // 2015): with Rhat the FP64-promoted R of the FP32 factorization,
-//     Y = A Rhat^{-1}   (row-wise forward substitution, FP64),
-//     G = Y^T Y = Rc^T Rc (Cholesky, FP64),
-//     R = Rc Rhat,  Q = Y Rc^{-1}.
-// Y has condition number 1 + O(u_32 kappa(A)), so the Cholesky step is well conditioned.
+//     Y = A Rhat^{-1}      (one MFMA product with the explicit inverse, stored),
+//     G = Y^T Y = Rc^T Rc  (MFMA Gram, Cholesky in FP64),
+//     R = Rc Rhat,  Q = Y Rc^{-1}  (a second MFMA product).
+// Y has condition number 1 + O(u_32 kappa(A)), so the Cholesky step is well conditioned, and
+// Q is formed from the same Y whose Gram gave Rc, which keeps Q^T Q = I to rounding.
 #include "tsqr_internal.h"
 
 namespace tsqr {
 namespace {
 
-constexpr int kRefineRows = 64;     // rows staged per step
-constexpr int kRefineBlocks = 512;  // work-groups of the Gram pass
-
-// y = a Rhat^{-1} for one row (a row vector; Rhat upper triangular, ld n, held in LDS)
-template <int NPM>
-__device__ __forceinline__ void row_solve(int n, const double *__restrict__ Rs, double (&y)[NPM])
+// Xinv = X^{-1} for an upper-triangular n x n X (ld ldx): thread j solves column j by back
+// substitution.  Skipped (left as garbage) when a diagonal entry is not positive; the caller's
+// info reports it.
+__device__ void tri_inv(int n, const double *__restrict__ X, int64_t ldx, double *__restrict__ Xinv)
 {
-#pragma unroll
-    for (int j = 0; j < NPM; ++j) {
-        if (j < n) {
-            double acc = y[j];
-#pragma unroll
-            for (int i = 0; i < NPM; ++i)
-                if (i < j) acc = fma(-y[i], Rs[i * n + j], acc);
-            y[j] = acc / Rs[j * n + j];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+        for (int i = n - 1; i > j; --i) Xinv[i * n + j] = 0.0;
+        for (int i = j; i >= 0; --i) {
+            double acc = (i == j) ? 1.0 : 0.0;
+            for (int t = i + 1; t <= j; ++t) acc = fma(-X[i * ldx + t], Xinv[t * n + j], acc);
+            Xinv[i * n + j] = acc / X[i * ldx + i];
         }
     }
 }
 
-template <int NPM>
-__global__ void __launch_bounds__(kThreads)
-k_refine_gram(int64_t m, int n, const double *__restrict__ A, int64_t lda,
-              const double *__restrict__ Rhat, double *__restrict__ Gpart)
+__global__ void __launch_bounds__(256)
+k_refine_rinv(int n, const double *__restrict__ Rhat, double *__restrict__ Rinv)
 {
-    __shared__ double Rs[NPM * NPM];
-    __shared__ double Ys[kRefineRows][NPM + 1];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += kThreads) Rs[e] = Rhat[e];
-    constexpr int kSlots = (NPM * NPM + kThreads - 1) / kThreads;
-    double acc[kSlots];
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) acc[s] = 0.0;
-    __syncthreads();
-    for (int64_t r0 = (int64_t)blockIdx.x * kRefineRows; r0 < m;
-         r0 += (int64_t)gridDim.x * kRefineRows) {
-        const int nr = (int)min((int64_t)kRefineRows, m - r0);
-        if (tid < kRefineRows) {
-            double y[NPM];
-#pragma unroll
-            for (int j = 0; j < NPM; ++j)
-                y[j] = (tid < nr && j < n) ? A[(r0 + tid) * lda + j] : 0.0;
-            if (tid < nr) row_solve<NPM>(n, Rs, y);
-#pragma unroll
-            for (int j = 0; j < NPM; ++j) Ys[tid][j] = (tid < nr) ? y[j] : 0.0;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const int e = tid + s * kThreads;
-            if (e < n * n) {
-                const int i = e / n, j = e - i * n;
-                double a = acc[s];
-                for (int r = 0; r < nr; ++r) a = fma(Ys[r][i], Ys[r][j], a);
-                acc[s] = a;
-            }
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int s = 0; s < kSlots; ++s) {
-        const int e = tid + s * kThreads;
-        if (e < n * n) Gpart[(int64_t)blockIdx.x * n * n + e] = acc[s];
-    }
+    tri_inv(n, Rhat, n, Rinv);
 }
 
-// G = sum of the partial Grams (fixed order), G = Rc^T Rc, R = Rc Rhat; Rc kept for the Q pass.
-__global__ void __launch_bounds__(kThreads)
-k_refine_chol(int n, int nblocks, const double *__restrict__ Gpart, const double *__restrict__ Rhat,
-              double *__restrict__ Rc, double *__restrict__ R, int64_t ldr, int32_t *info)
+// G = Rc^T Rc (right-looking Cholesky in LDS), R = Rc Rhat, Rcinv = Rc^{-1}; info = -2 when G
+// is not positive definite.
+__global__ void __launch_bounds__(256)
+k_refine_chol(int n, const double *__restrict__ G, const double *__restrict__ Rhat,
+              double *__restrict__ Rc, double *__restrict__ Rcinv, double *__restrict__ R,
+              int64_t ldr, int32_t *info)
 {
     extern __shared__ double Gs[];   // n x n
     __shared__ int s_fail;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, nth = blockDim.x;
     if (tid == 0) s_fail = 0;
-    for (int e = tid; e < n * n; e += kThreads) {
-        double a = 0.0;
-        for (int b = 0; b < nblocks; ++b) a += Gpart[(int64_t)b * n * n + e];
-        Gs[e] = a;
-    }
+    for (int e = tid; e < n * n; e += nth) Gs[e] = G[e];
     __syncthreads();
-    // right-looking Cholesky, upper factor in the upper triangle of Gs
     for (int k = 0; k < n; ++k) {
         const double d = Gs[k * n + k];
         if (!(d > 0.0)) {
@@ -102,22 +56,23 @@ k_refine_chol(int n, int nblocks, const double *__restrict__ Gpart, const double
         }
         const double rkk = sqrt(d);
         __syncthreads();
-        for (int j = k + tid; j < n; j += kThreads) Gs[k * n + j] = (j == k) ? rkk : Gs[k * n + j] / rkk;
+        for (int j = k + tid; j < n; j += nth) Gs[k * n + j] = (j == k) ? rkk : Gs[k * n + j] / rkk;
         __syncthreads();
-        for (int e = tid; e < (n - k - 1) * (n - k - 1); e += kThreads) {
-            const int i = k + 1 + e / (n - k - 1), j = k + 1 + e % (n - k - 1);
+        const int w = n - k - 1;
+        for (int e = tid; e < w * w; e += nth) {
+            const int i = k + 1 + e / w, j = k + 1 + e % w;
             if (j >= i) Gs[i * n + j] -= Gs[k * n + i] * Gs[k * n + j];
         }
         __syncthreads();
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += kThreads) {
+    for (int e = tid; e < n * n; e += nth) {
         const int i = e / n, j = e - i * n;
-        const double rc = (j >= i) ? Gs[e] : 0.0;
-        Rc[e] = rc;
+        Rc[e] = (j >= i) ? Gs[e] : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < n * n; e += kThreads) {
+    tri_inv(n, Rc, n, Rcinv);
+    for (int e = tid; e < n * n; e += nth) {
         const int i = e / n, j = e - i * n;
         double a = 0.0;
         if (j >= i)
@@ -127,67 +82,43 @@ k_refine_chol(int n, int nblocks, const double *__restrict__ Gpart, const double
     if (tid == 0 && s_fail) *info = -2;
 }
 
-template <int NPM>
-__global__ void __launch_bounds__(kThreads)
-k_refine_q(int64_t m, int n, const double *__restrict__ A, int64_t lda,
-           const double *__restrict__ Rhat, const double *__restrict__ Rc, double *__restrict__ Q,
-           int64_t ldq)
-{
-    __shared__ double Rs[NPM * NPM];
-    __shared__ double Cs[NPM * NPM];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += kThreads) { Rs[e] = Rhat[e]; Cs[e] = Rc[e]; }
-    __syncthreads();
-    for (int64_t r = (int64_t)blockIdx.x * kThreads + tid; r < m; r += (int64_t)gridDim.x * kThreads) {
-        double y[NPM];
-#pragma unroll
-        for (int j = 0; j < NPM; ++j) y[j] = (j < n) ? A[r * lda + j] : 0.0;
-        row_solve<NPM>(n, Rs, y);
-        row_solve<NPM>(n, Cs, y);
-#pragma unroll
-        for (int j = 0; j < NPM; ++j)
-            if (j < n) Q[r * ldq + j] = y[j];
-    }
-}
+constexpr int kRefPanel = 256;   // rows per work-group of the two products
 
 }  // namespace
 
 int refine_blocks(int64_t m, int64_t n)
 {
     (void)n;
-    int64_t b = ceil_div(m, kRefineRows);
-    return (int)(b < kRefineBlocks ? b : kRefineBlocks);
+    return gram_blocks(m);
 }
 
 size_t refine_scratch_bytes(int64_t m, int64_t n)
 {
-    // partial Grams + Rc
-    return sizeof(double) * ((size_t)refine_blocks(m, n) * n * n + (size_t)n * n);
+    // Y (m x n), Gram partials, G, Rinv, Rc, Rcinv (n x n each)
+    const size_t nn = (size_t)n * n;
+    return sizeof(double) * ((size_t)m * n + (size_t)refine_blocks(m, n) * nn + 4 * nn) + 1024;
 }
 
 hipError_t launch_refine(int64_t m, int64_t n, const double *A, int64_t lda, double *Rhat,
                          double *Q, int64_t ldq, double *R, int64_t ldr, void *scratch,
                          int32_t *info, hipStream_t st)
 {
-    const int nb = refine_blocks(m, n);
-    double *Gpart = (double *)scratch;
-    double *Rc = Gpart + (size_t)nb * n * n;
-    const int qblocks = (int)((m + kThreads - 1) / kThreads < 2048 ? (m + kThreads - 1) / kThreads : 2048);
-#define TSQR_REFINE_CASE(NPM)                                                                   \
-    do {                                                                                        \
-        hipLaunchKernelGGL((k_refine_gram<NPM>), dim3(nb), dim3(kThreads), 0, st, m, (int)n, A,   \
-                           lda, Rhat, Gpart);                                                   \
-        hipLaunchKernelGGL(k_refine_chol, dim3(1), dim3(kThreads), sizeof(double) * n * n, st,   \
-                           (int)n, nb, Gpart, Rhat, Rc, R, ldr, info);                          \
-        hipLaunchKernelGGL((k_refine_q<NPM>), dim3(qblocks), dim3(kThreads), 0, st, m, (int)n, A, \
-                           lda, Rhat, Rc, Q, ldq);                                              \
-    } while (0)
-    if (n <= 16) TSQR_REFINE_CASE(16);
-    else if (n <= 32) TSQR_REFINE_CASE(32);
-    else if (n <= 64) TSQR_REFINE_CASE(64);
-    else return hipErrorInvalidValue;
-#undef TSQR_REFINE_CASE
-    return hipGetLastError();
+    if (n > 64) return hipErrorInvalidValue;
+    const size_t nn = (size_t)n * n;
+    double *Y = (double *)scratch;
+    double *part = Y + (size_t)m * n;
+    double *G = part + (size_t)refine_blocks(m, n) * nn;
+    double *Rinv = G + nn, *Rc = Rinv + nn, *Rcinv = Rc + nn;
+    hipLaunchKernelGGL(k_refine_rinv, dim3(1), dim3(256), 0, st, (int)n, Rhat, Rinv);
+    hipError_t e = launch_gemm_mfma(F64, F64, m, n, kRefPanel, A, lda, Rinv, n, 0, (int)n, Y, n,
+                                    (int)n, nullptr, 0, 0, st);
+    if (e != hipSuccess) return e;
+    if ((e = launch_gram(m, n, Y, n, Y, n, part, G, st)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_refine_chol, dim3(1), dim3(256), sizeof(double) * nn, st, (int)n, G, Rhat,
+                       Rc, Rcinv, R, ldr, info);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return launch_gemm_mfma(F64, F64, m, n, kRefPanel, Y, n, Rcinv, n, 0, (int)n, Q, ldq, (int)n,
+                            nullptr, 0, 0, st);
 }
 
 }  // namespace tsqr
