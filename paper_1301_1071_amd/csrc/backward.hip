@@ -106,16 +106,46 @@ k_gram_sum(int64_t nn, const double *__restrict__ part, int nblk, double *__rest
     G[e] = a;
 }
 
-// Rinv = R^{-1} (R upper triangular, n x n): thread j solves R x = e_j by back substitution.
+// v summed over the 64 lanes of the wave (every lane gets the sum)
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Rinv = R^{-1} (R upper triangular, n x n, n <= 128): one wave per column j solves R x = e_j by
+// back substitution; lane t keeps x_t and x_{t+64} in registers, so each step is two FMAs, a
+// wave sum and one division, with the next row of R fetched while the current step reduces.
 __device__ void tri_inverse(int n, const double *R, double *Rinv)
 {
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-        for (int i = n - 1; i > j; --i) Rinv[i * n + j] = 0.0;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
+    for (int j = wave; j < n; j += nwaves) {
+        double x0 = 0.0, x1 = 0.0;                       // x_lane, x_{lane+64}
+        double r0 = (lane <= j) ? R[j * n + lane] : 0.0;
+        double r1 = (lane + 64 <= j) ? R[j * n + lane + 64] : 0.0;
         for (int i = j; i >= 0; --i) {
-            double acc = (i == j) ? 1.0 : 0.0;
-            for (int t = i + 1; t <= j; ++t) acc = fma(-R[i * n + t], Rinv[t * n + j], acc);
-            Rinv[i * n + j] = acc / R[i * n + i];
+            // prefetch row i - 1 (columns up to j)
+            double n0 = 0.0, n1 = 0.0;
+            if (i > 0) {
+                n0 = (lane <= j) ? R[(i - 1) * n + lane] : 0.0;
+                n1 = (lane + 64 <= j) ? R[(i - 1) * n + lane + 64] : 0.0;
+            }
+            // sum_{t > i} R[i][t] x_t (x_t = 0 for t > j or not yet computed)
+            double part = 0.0;
+            if (lane > i) part = fma(r0, x0, part);
+            if (lane + 64 > i) part = fma(r1, x1, part);
+            const double s = wave_sum(part);
+            const double rii = __shfl(i < 64 ? r0 : r1, i & 63, 64);
+            const double xi = (((i == j) ? 1.0 : 0.0) - s) / rii;
+            if (lane == i) x0 = xi;
+            if (lane + 64 == i) x1 = xi;
+            r0 = n0;
+            r1 = n1;
         }
+        if (lane < n) Rinv[lane * n + j] = (lane <= j) ? x0 : 0.0;
+        if (lane + 64 < n) Rinv[(lane + 64) * n + j] = (lane + 64 <= j) ? x1 : 0.0;
     }
 }
 
