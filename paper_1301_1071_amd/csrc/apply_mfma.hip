@@ -60,9 +60,10 @@ hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t 
 #define TSQR_NT(NT)                                                                          \
     return apply_mfma_nt<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1, \
                                     ld1, acc, st)
-    // at most 4 tiles (64 columns) per work-group: wider outputs take several slices, which
-    // keeps the LDS image of W small enough for three work-groups per CU
-    if (tiles <= 2) TSQR_NT(2);
+    // at most 4 tiles (64 columns) per work-group, 2 for n > 64: wider outputs take several
+    // slices on the same XCD, which keeps the LDS image of W small enough for three work-groups
+    // per CU (measured: 4 tiles are faster at n = 50, 2 tiles at n = 100)
+    if (tiles <= 2 || n > 64) TSQR_NT(2);
     TSQR_NT(4);
 #undef TSQR_NT
 }
