@@ -9,19 +9,19 @@ namespace blklaunch {
 
 using blkpanel::BlkSmem;
 
-// Panel shapes (no register spills; two work-groups per CU up to n = 64): 4 waves with 256
-// rows for 32 < n <= 64 and 384 rows for n <= 32; 8 waves with 256 rows for 64 < n <= 128
-// (one work-group per CU).  FP32 uses the same shapes.
+// Panel shapes (no register spills): 4 waves with 384 rows for n <= 32 (two work-groups per
+// CU); 8 waves with 512 rows for 32 < n <= 64 and 256 rows for 64 < n <= 128 (one work-group per
+// CU).  FP32 uses the same shapes.
 template <typename T, int NCT> struct BlkShape {
-    static constexpr int NW = (NCT <= 4) ? 4 : 8;
+    static constexpr int NW = (NCT <= 2) ? 4 : 8;
     static constexpr int RT = (NCT <= 2) ? 6 : ((NCT <= 4) ? 4 : 2);
-    static constexpr int TC = (NCT <= 4) ? NCT : 2;
+    static constexpr int TC = (NCT <= 2) ? NCT : 2;
     static constexpr int B = NW * RT * 16;
     static constexpr size_t LDS = sizeof(BlkSmem<T, NCT, RT, NW, TC>);
 };
 
 template <typename Tin, typename T, int NCT>
-__global__ void __launch_bounds__((NCT <= 4) ? 256 : 512, (NCT <= 4) ? 2 : 1)
+__global__ void __launch_bounds__((NCT <= 2) ? 256 : 512, (NCT <= 2) ? 2 : 1)
 k_factor_blk(int64_t rows, int n, const Tin *__restrict__ X, int64_t ldx, T *__restrict__ q1,
              double *__restrict__ S)
 {
