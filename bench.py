@@ -331,6 +331,7 @@ def bench_batched(args, dtype):
 # (scaled by the copy calibration) for the kernels as they are now; the summaries with the
 # commands are in profiles/.  Keyed by (workload, kernel class).
 MEASURED_TRAFFIC = {
+    ("svd-c50", "factor_level0"): 3.537e9,      # profiles/factor_blk_svd-c50.md
 }
 
 
