@@ -35,12 +35,23 @@ __device__ __forceinline__ double rsqrt_nr(double x)
 
 constexpr int kSvdThreads = 1024;   // 16 waves: 64 groups of 16 lanes, one column pair each
 
-// reduce over the 16 lanes of a group (xor offsets 8..1 stay inside the group)
+template <int CTRL> __device__ __forceinline__ double dpp_d(double v)
+{
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over the 16 lanes of a group (one DPP row): butterflies within quads, rotations by 4 and 8
+// across the quads, then lane 0's sum broadcast to the row so every lane of the group takes the
+// same rotation decision.
 __device__ __forceinline__ double group16_sum(double v)
 {
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    v += dpp_d<0xB1>(v);          // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);          // quad_perm [2,3,0,1]
+    v += dpp_d<0x124>(v);         // row_ror:4
+    v += dpp_d<0x128>(v);         // row_ror:8
+    return dpp_d<0x150>(v);       // row_newbcast:0
 }
 
 __global__ void __launch_bounds__(kSvdThreads)
