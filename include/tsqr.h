@@ -24,7 +24,7 @@
  *   - The factorization is the unique thin QR with diag(R) > 0 (A full rank).  Q is m x n with
  *     orthonormal columns, R is n x n upper triangular (strict lower triangle written as 0).
  *   - Supported: 1 <= n <= TSQR_NMAX, m >= n.  Values must be well inside the floating-point
- *     range (|a_ij| < 1e150 in FP64, < 1e18 in FP32): column norms are formed without scaling.
+ *     range (|a_ij| < 1e150 in FP64, < 1e17 in FP32): column norms are formed without scaling.
  */
 #ifndef TSQR_H
 #define TSQR_H

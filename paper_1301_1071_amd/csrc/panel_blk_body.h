@@ -337,19 +337,20 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
                 pc += sm.part[par][ww][lc];
             }
             const T alpha = sm.rowk[par][kk];
-            T tau = T(0), u = T(0), beta = alpha;
+            // one reciprocal per step: with r = 1 / (u beta), tau = (beta - alpha)/beta = -u^2 r
+            // and the coefficient tau (a_kc + pc/u)/u of column c is -(a_kc u + pc) r
+            T tau = T(0), u = T(0), beta = alpha, r = T(0);
             if (s2 != T(0)) {
                 const T nrm = sqrt(alpha * alpha + s2);
                 beta = (alpha >= T(0)) ? -nrm : nrm;
-                tau = T(1) - alpha * K::rcp(beta);
                 u = alpha - beta;
+                r = K::rcp(u * beta);
+                tau = -u * u * r;
             }
             if (tid == 0) { sm.tau[k] = tau; sm.u[k] = u; sm.beta[k] = beta; }
             T coef = T(0);
-            if (tau != T(0) && lc > kk && 16 * kt + lc < n) {
-                const T inv = K::rcp(u);
-                coef = tau * (sm.rowk[par][lc] + inv * pc) * inv;
-            }
+            if (s2 != T(0) && lc > kk && 16 * kt + lc < n)
+                coef = -fma(sm.rowk[par][lc], u, pc) * r;
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 const int gt = rt * NW + w;
