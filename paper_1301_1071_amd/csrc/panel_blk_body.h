@@ -47,11 +47,12 @@ template <> struct BlkT<double> {
     static constexpr __host__ __device__ int rit(int lr, int i) { return lr + 4 * i; }
     static constexpr __host__ __device__ int kk_lr(int kk) { return kk & 3; }
     static constexpr __host__ __device__ int kk_i(int kk) { return kk >> 2; }
-    // value of lane KK of this lane's 16-lane row (DPP row_newbcast)
+    // value of lane KK of this lane's 16-lane row (DPP row_newbcast). Every lane reads a valid
+    // source lane, so the old value is never used: bound_ctrl lets the compiler skip zeroing it.
     template <int KK> static __device__ __forceinline__ double bcast16(double v)
     {
-        const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x150 + KK, 0xf, 0xf, false);
-        const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x150 + KK, 0xf, 0xf, false);
+        const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), 0x150 + KK, 0xf, 0xf, true);
+        const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), 0x150 + KK, 0xf, 0xf, true);
         return __hiloint2double(hi, lo);
     }
     // v[l] + v[l ^ 16] and v[l] + v[l ^ 32] through the gfx950 lane-swap instructions (the two
@@ -87,7 +88,7 @@ template <> struct BlkT<float> {
     static constexpr __host__ __device__ int kk_i(int kk) { return kk & 3; }
     template <int KK> static __device__ __forceinline__ float bcast16(float v)
     {
-        return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + KK, 0xf, 0xf, false));
+        return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x150 + KK, 0xf, 0xf, true));
     }
     static __device__ __forceinline__ float sum_xor16(float v)
     {

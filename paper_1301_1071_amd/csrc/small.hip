@@ -35,10 +35,12 @@ __device__ __forceinline__ double rsqrt_nr(double x)
 
 constexpr int kSvdThreads = 1024;   // 16 waves: 64 groups of 16 lanes, one column pair each
 
+// DPP lane move; the patterns used here (quad_perm, row_ror, row_newbcast) read a valid lane for
+// every lane, so the old value is never used and needs no zeroing (bound_ctrl)
 template <int CTRL> __device__ __forceinline__ double dpp_d(double v)
 {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xf, 0xf, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xf, 0xf, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xf, 0xf, true);
     return __hiloint2double(hi, lo);
 }
 
