@@ -55,16 +55,29 @@ hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t 
                         const double *W, int64_t ldw, int64_t wstride, int k, void *out0,
                         int64_t ld0, int k0, void *out1, int64_t ld1, int acc, hipStream_t st)
 {
-    // one work-group covers up to 16 * NT output columns
+    // Column slices per panel: as few as keep a work-group within 8 output tiles and 80 KB of
+    // LDS (the W image plus the staged Q1 blocks), so that two work-groups share a CU.  Every
+    // slice stages the panel's Q1 rows again (from the XCD's L2), so fewer slices read less.
     const int tiles = (int)ceil_div(k, 16);
-#define TSQR_NT(NT)                                                                          \
-    return apply_mfma_nt<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1, \
-                                    ld1, acc, st)
-    // at most 4 tiles (64 columns) per work-group, 2 for n > 64: wider outputs take several
-    // slices on the same XCD, which keeps the LDS image of W small enough for three work-groups
-    // per CU (measured: 4 tiles are faster at n = 50, 2 tiles at n = 100)
-    if (tiles <= 2 || n > 64) TSQR_NT(2);
-    TSQR_NT(4);
+    int ny = 1;
+    auto nt_of = [&](int y) { return (int)ceil_div(tiles, y); };
+    while (ny < tiles && (nt_of(ny) > 8 || apply_lds_bytes_nt(sizeof(T), n, nt_of(ny)) > 80 * 1024))
+        ++ny;
+#define TSQR_NT(NT)                                                                           \
+    case NT:                                                                                  \
+        return apply_mfma_nt<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, \
+                                        out1, ld1, acc, st)
+    switch (nt_of(ny)) {
+        TSQR_NT(1);
+        TSQR_NT(2);
+        TSQR_NT(3);
+        TSQR_NT(4);
+        TSQR_NT(5);
+        TSQR_NT(6);
+        TSQR_NT(7);
+        TSQR_NT(8);
+    default: return hipErrorInvalidValue;
+    }
 #undef TSQR_NT
 }
 

@@ -39,13 +39,15 @@ template <> struct Mfma<float> {
 constexpr int kMaxKC = 32;      // n <= 128
 constexpr int kWaves = 4;
 
-template <typename T, typename To, int NT>
-__device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
+// One panel.  ACC: add to the output instead of overwriting it; WIDE: n > 64 (lane l also holds
+// column l + 64 of a row).
+template <typename T, typename To, int NT, bool ACC, bool WIDE>
+__device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
                                                  const T *__restrict__ q1, int64_t ldq,
                                                  const double *__restrict__ W, int64_t ldw,
                                                  int64_t wstride, int k, To *__restrict__ out0,
                                                  int64_t ld0, int k0, To *__restrict__ out1,
-                                                 int64_t ld1, int accumulate, int64_t p, int j0)
+                                                 int64_t ld1, int64_t p, int j0)
 {
     typedef typename Mfma<T>::acc_t acc_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -59,42 +61,80 @@ __device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
     T *as = as_all + (size_t)w * 16 * LDA;
     const double *Wp = W + p * wstride * ldw;
 
-    for (int e = tid; e < KC * NT * 64; e += kWaves * 64) {
-        const int l = e & 63, t = e >> 6;
-        const int nt = t % NT, kc = t / NT;
-        const int kk = 4 * kc + (l >> 4), j = j0 + 16 * nt + (l & 15);
-        wl[e] = (kk < n && j < k) ? (T)Wp[(int64_t)kk * ldw + j] : T(0);
-    }
-    // zero this wave's staging block once: columns [n, 4 KC) stay zero
-    for (int e = lane; e < 16 * LDA; e += 64) as[e] = T(0);
-    __syncthreads();
-
     const int64_t rb = p * (int64_t)b;
     const int nr = (int)min((int64_t)b, rows - rb);
     const int nblk = (nr + 15) >> 4;
-    const int jl = j0 + (lane & 15);
-    // The 16 x n blocks of Q1 are fetched one block ahead into registers (lane owns columns
-    // lane and lane + 64 of every row), so the next block's loads are in flight during this
-    // block's products; each block is then staged through this wave's LDS rows.
-    T pre[16], pre2[16];
+    // The 16 x n blocks of Q1 are fetched one block ahead into registers (lane l holds columns
+    // l and, if WIDE, l + 64 of every row), so the next block's loads are in flight during this
+    // block's products; each block is then staged through this wave's LDS rows.  Every load is
+    // in bounds: a lane past column n reads column n - 1 and rows past the panel read its last
+    // row; neither reaches LDS or an output row.
+    const bool ok0 = lane < n, ok1 = WIDE && lane + 64 < n;
+    const uint32_t c0 = ok0 ? lane : n - 1, c1 = ok1 ? lane + 64 : n - 1;
+    T pre[16], pre2[WIDE ? 16 : 1];
     auto fetch = [&](int blk) {
-        const int r0 = blk * 16;
-        const int cnt = min(16, nr - r0);
-        const T *src = q1 + (rb + r0) * ldq;
+        const int last = min(16, nr - blk * 16) - 1;
+        const T *src = q1 + (rb + blk * 16) * ldq;
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-            pre[r] = (r < cnt && lane < n) ? src[(int64_t)r * ldq + lane] : T(0);
-            pre2[r] = (r < cnt && lane + 64 < n) ? src[(int64_t)r * ldq + lane + 64] : T(0);
+            const T *row = src + (int64_t)min(r, last) * ldq;      // uniform
+            pre[r] = row[c0];
+            if constexpr (WIDE) pre2[r] = row[c1];
         }
     };
+    // W's loads go out eight at a time, so staging it waits for a few memory round trips rather
+    // than one per value; the first block's loads are issued right after, before the barrier
+    {
+        constexpr int U = 8;
+        const int total = KC * NT * 64;
+        for (int e0 = tid; e0 < total; e0 += U * kWaves * 64) {
+            T v[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * kWaves * 64;
+                const int l = e & 63, t = e >> 6;
+                const int nt = t % NT, kc = t / NT;
+                const int kk = 4 * kc + (l >> 4), j = j0 + 16 * nt + (l & 15);
+                // unconditional load at a clamped (in-bounds) index, then a select: no branch
+                // around the load, so the eight loads stay in flight together
+                const double x = Wp[(int64_t)min(kk, n - 1) * ldw + min(j, k - 1)];
+                v[u] = (e < total && kk < n && j < k) ? (T)x : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int e = e0 + u * kWaves * 64;
+                if (e < total) wl[e] = v[u];
+            }
+        }
+    }
     if (w < nblk) fetch(w);
+    // zero this wave's staging block once: columns [n, 4 KC) stay zero
+    for (int e = lane; e < 16 * LDA; e += 64) as[e] = T(0);
+    __syncthreads();
+    const int jl = j0 + (lane & 15);
+    const T *ap = as + (lane & 15) * LDA + (lane >> 4);
+    const T *wk = wl + lane;
+    // output element i of a tile: row Mfma::row(lane, i) of the block, column jl + 16 t; the
+    // lane's offsets from the block's first row are fixed, the block base is uniform
+    int64_t off0[4], off1[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = Mfma<T>::row(lane, i);
+        off0[i] = r * ld0 + jl;
+        off1[i] = r * ld1 + jl - k0;
+    }
     for (int blk = w; blk < nblk; blk += kWaves) {
         const int r0 = blk * 16;
         const int cnt = min(16, nr - r0);
+        if (ok0) {
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-            if (lane < n) as[r * LDA + lane] = pre[r];
-            if (lane + 64 < n) as[r * LDA + lane + 64] = pre2[r];
+            for (int r = 0; r < 16; ++r) as[r * LDA + lane] = pre[r];
+        }
+        if constexpr (WIDE) {
+            if (ok1) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) as[r * LDA + lane + 64] = pre2[r];
+            }
         }
         if (blk + kWaves < nblk) fetch(blk + kWaves);
         // the wave reads back what its own lanes wrote: LDS operations of a wave are ordered
@@ -102,42 +142,64 @@ __device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
 #pragma unroll
         for (int t = 0; t < NT; ++t) acc[t] = acc_t{0, 0, 0, 0};
         for (int kc = 0; kc < KC; ++kc) {
-            const T a = as[(lane & 15) * LDA + 4 * kc + (lane >> 4)];
-            const T *wk = wl + (size_t)kc * NT * 64 + lane;
+            const T a = ap[4 * kc];
 #pragma unroll
-            for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::run(a, wk[t * 64], acc[t]);
+            for (int t = 0; t < NT; ++t) acc[t] = Mfma<T>::run(a, wk[(kc * NT + t) * 64], acc[t]);
         }
-        // results: row pointers once per block, then a column offset per tile
-        To *o0[4], *o1[4];
-        bool rok[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int r = Mfma<T>::row(lane, i);
-            rok[i] = r < cnt;
-            const int64_t gr = rb + r0 + (rok[i] ? r : 0);
-            o0[i] = out0 + gr * ld0;
-            o1[i] = out1 ? out1 + gr * ld1 - k0 : nullptr;
-        }
+        // columns below k0 go to out0, the rest to out1 (shifted by k0); a tile lies on one
+        // side of k0 except at most one, which selects per lane
+        To *const b0 = out0 + (rb + r0) * ld0;
+        To *const b1 = out1 ? out1 + (rb + r0) * ld1 : b0;
+        auto put = [&](To *o, T v) {
+            if constexpr (ACC) *o = (To)(v + (T)*o);
+            else *o = (To)v;
+        };
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            const int j = jl + 16 * t;
-            if (j >= k) continue;
-            const bool first = j < k0;
+            const int jt = j0 + 16 * t;                 // uniform first column of the tile
+            if (jt >= k) break;
+            const bool jok = jl + 16 * t < k;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                if (!rok[i]) continue;
-                To *o = (first ? o0[i] : o1[i]) + j;
-                *o = accumulate ? (To)(acc[t][i] + (T)*o) : (To)acc[t][i];
+                if (!(jok && Mfma<T>::row(lane, i) < cnt)) continue;
+                if (jt + 16 <= k0) put(b0 + off0[i] + 16 * t, acc[t][i]);
+                else if (jt >= k0) put(b1 + off1[i] + 16 * t, acc[t][i]);
+                else put(jl + 16 * t < k0 ? b0 + off0[i] + 16 * t : b1 + off1[i] + 16 * t,
+                         acc[t][i]);
             }
         }
     }
 }
 
-// Dynamic LDS of one work-group for n columns and NT output tiles.
-template <typename T, int NT> inline size_t apply_lds_bytes(int64_t n)
+template <typename T, typename To, int NT>
+__device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
+                                                 const T *__restrict__ q1, int64_t ldq,
+                                                 const double *__restrict__ W, int64_t ldw,
+                                                 int64_t wstride, int k, To *__restrict__ out0,
+                                                 int64_t ld0, int k0, To *__restrict__ out1,
+                                                 int64_t ld1, int accumulate, int64_t p, int j0)
+{
+#define TSQR_APPLY(ACC, WIDE)                                                                   \
+    apply_panel_impl<T, To, NT, ACC, WIDE>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, \
+                                           k0, out1, ld1, p, j0)
+    if (n > 64) {
+        if (accumulate) TSQR_APPLY(true, true);
+        else TSQR_APPLY(false, true);
+    } else {
+        if (accumulate) TSQR_APPLY(true, false);
+        else TSQR_APPLY(false, false);
+    }
+#undef TSQR_APPLY
+}
+
+inline size_t apply_lds_bytes_nt(size_t elem, int64_t n, int nt)
 {
     const int KC = (int)((n + 3) / 4);
-    return sizeof(T) * ((size_t)KC * NT * 64 + (size_t)kWaves * 16 * (4 * KC + 1));
+    return elem * ((size_t)KC * nt * 64 + (size_t)kWaves * 16 * (4 * KC + 1));
+}
+template <typename T, int NT> inline size_t apply_lds_bytes(int64_t n)
+{
+    return apply_lds_bytes_nt(sizeof(T), n, NT);
 }
 
 }  // namespace mfmaapply
