@@ -21,8 +21,12 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 # Packed-FP32 instructions are disabled (the feature is switched off for the device pass; the
 # host pass warns that it does not know the feature, which is harmless).
+# MFMA accumulators stay in ordinary VGPRs (-amdgpu-mfma-vgpr-form): with AGPR-form MFMA the
+# compiler kept loop-carried accumulators in VGPRs and copied them to AGPRs and back around every
+# MFMA group, which also drained the matrix pipeline each iteration.
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-mcode-object-version=5",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+          "-mllvm", "-amdgpu-mfma-vgpr-form",
           "-Wno-unused-command-line-argument", "-Wno-unknown-cuda-version",
           "-I", os.path.join(HERE, "..", "include")]
 
