@@ -109,6 +109,7 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
         const int npairs = np / 2;
         const int grp = tid >> 4, gl = tid & 15;       // 16-lane group and lane within it
         const int ngrp = nth >> 4;
+        const int nj = (n + 15) >> 4;                  // 16-row chunks of a column
         const double tol = 1e-15 * (double)n;
         const double tol2 = tol * tol;
         for (int sweep = 0; sweep < 60; ++sweep) {
@@ -125,6 +126,7 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
                     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
                     for (int j = 0; j < kNmaxPad / 16; ++j) {
+                        if (j >= nj) break;                    // uniform: chunks past n
                         const int i = gl + 16 * j;
                         xp[j] = (i < n) ? gp[i] : 0.0;
                         xq[j] = (i < n) ? gq[i] : 0.0;
@@ -144,6 +146,7 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
                         double *vp = gV + (int64_t)p * n, *vq = gV + (int64_t)q * n;
 #pragma unroll
                         for (int j = 0; j < kNmaxPad / 16; ++j) {
+                            if (j >= nj) break;
                             const int i = gl + 16 * j;
                             if (i < n) {
                                 gp[i] = cs * xp[j] - sn * xq[j];
@@ -215,7 +218,11 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
         if (e != hipSuccess) return e;
         attr_bytes = lds;
     }
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kSvdThreads), lds, st, (int)n, Rt, R,
+    // one 16-lane group per column pair of a Jacobi round, whole waves, so that each round's
+    // barrier waits only for waves that have work
+    const int64_t pairs = (n + (n & 1)) / 2;
+    const int threads = (int)std::min<int64_t>(kSvdThreads, std::max<int64_t>(64, (16 * pairs + 63) / 64 * 64));
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(threads), lds, st, (int)n, Rt, R,
                        Rf, ldr, Wtop, k, want_q, want_u, S, V, ldv, G, Vw, use_lds, info);
     return hipGetLastError();
 }
