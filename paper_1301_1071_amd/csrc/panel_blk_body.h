@@ -227,24 +227,30 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
     };
 
     // T of block KT (Q_blk = H_1 ... H_16 = I - V T V^T) from G = wsum[KT] = V^T V by the
-    // column recurrence T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], T[j][j] = tau_j: lane i of wave
-    // 0 computes row i of T, which needs only entries of its own row (read back from LDS in
-    // program order), so no barrier is needed inside.  Ends with a barrier.
+    // column recurrence T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], T[j][j] = tau_j.  Row i of T
+    // needs only earlier entries of row i, so wave 0 computes all rows at once: lane (i, q) =
+    // i + 16 q holds T[i][l] for the columns l = q mod 4 in registers (zero until computed, and
+    // zero below the diagonal), forms its share of the sum over l < j, and the four shares of a
+    // row are added with the lane swaps.  Ends with a barrier.
     auto block_t = [&](auto KT) {
         constexpr int kt = decltype(KT)::value;
-        if (w == 0 && lane < 16) {
-            const int i = lane;
-            T *trow = sm.tstore[kt][i];
-            for (int j = 0; j < 16; ++j) {
+        if (w == 0) {
+            const int i = lane & 15, q = lane >> 4;
+            const T *gq = &sm.wsum[kt][q * 16];             // row q of G; row 4m + q at +64 m
+            T tr[4] = {T(0), T(0), T(0), T(0)};
+            static_for<0, 16>([&](auto J) {
+                constexpr int j = decltype(J)::value;
                 const int cj = 16 * kt + j;
                 const T tj = (cj < n) ? sm.tau[cj] : T(0);
-                T s0 = T(0), s1 = T(0);
-                for (int l = i; l < j; l += 2) {
-                    s0 = fma(trow[l], sm.wsum[kt][l * 16 + j], s0);
-                    if (l + 1 < j) s1 = fma(trow[l + 1], sm.wsum[kt][(l + 1) * 16 + j], s1);
-                }
-                trow[j] = (i < j) ? -tj * (s0 + s1) : ((i == j) ? tj : T(0));
-            }
+                T part = T(0);
+#pragma unroll
+                for (int m = 0; m < 4; ++m) part = fma(tr[m], gq[64 * m + j], part);
+                const T sum = K::sum_xor32(K::sum_xor16(part));
+                const T tij = (i < j) ? -tj * sum : ((i == j) ? tj : T(0));
+                if (q == (j & 3)) tr[j >> 2] = tij;
+            });
+#pragma unroll
+            for (int m = 0; m < 4; ++m) sm.tstore[kt][i][4 * m + q] = tr[m];
         }
         __syncthreads();
     };
