@@ -337,27 +337,40 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
             const T d = K::sum_xor32(K::sum_xor16(d0 + d1));
             if (lr == 0) sm.part[par][w][lc] = d;
             __syncthreads();
-            T s2 = T(0), pc = T(0);
+            // the waves' partials, all read at once and added pairwise (NW is a power of two);
+            // pc and the pivot row entry of column lc are ready before the norm is
+            T ps[NW], pp[NW];
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
-                s2 += sm.part[par][ww][kk];
-                pc += sm.part[par][ww][lc];
+                ps[ww] = sm.part[par][ww][kk];
+                pp[ww] = sm.part[par][ww][lc];
             }
             const T alpha = sm.rowk[par][kk];
+            const T rowc = sm.rowk[par][lc];
+#pragma unroll
+            for (int h = NW / 2; h >= 1; h /= 2)
+#pragma unroll
+                for (int ww = 0; ww < h; ++ww) {
+                    ps[ww] += ps[ww + h];
+                    pp[ww] += pp[ww + h];
+                }
+            const T s2 = ps[0], pc = pp[0];
             // one reciprocal per step: with r = 1 / (u beta), tau = (beta - alpha)/beta = -u^2 r
             // and the coefficient tau (a_kc + pc/u)/u of column c is -(a_kc u + pc) r
-            T tau = T(0), u = T(0), beta = alpha, r = T(0);
-            if (s2 != T(0)) {
-                const T nrm = sqrt(alpha * alpha + s2);
-                beta = (alpha >= T(0)) ? -nrm : nrm;
-                u = alpha - beta;
-                r = K::rcp(u * beta);
-                tau = -u * u * r;
-            }
-            if (tid == 0) { sm.tau[k] = tau; sm.u[k] = u; sm.beta[k] = beta; }
-            T coef = T(0);
-            if (s2 != T(0) && lc > kk && 16 * kt + lc < n)
-                coef = -fma(sm.rowk[par][lc], u, pc) * r;
+            // Computed without a branch and then selected (s2 = 0: no reflection, tau = 0), so
+            // the sum for pc can overlap the square root; the discarded values of that case
+            // (a reciprocal of zero) never reach a result.
+            const bool live = s2 != T(0);
+            const T nrm = sqrt(alpha * alpha + s2);
+            const T bl = (alpha >= T(0)) ? -nrm : nrm;
+            const T ul = alpha - bl;
+            const T rl = K::rcp(ul * bl);
+            const T beta = live ? bl : alpha;
+            const T u = live ? ul : T(0);
+            const T r = live ? rl : T(0);
+            const T tau = live ? -ul * ul * rl : T(0);
+            const T cl = -fma(rowc, u, pc) * r;
+            const T coef = (live && lc > kk && 16 * kt + lc < n) ? cl : T(0);
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 const int gt = rt * NW + w;
@@ -372,6 +385,8 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
                     }
                 }
             }
+            // read only after the barrier that ends the block (each step writes its own slot)
+            if (tid == 0) { sm.tau[k] = tau; sm.u[k] = u; sm.beta[k] = beta; }
         });
         __syncthreads();      // tau, u of the block visible to every wave
         if constexpr (kt + 1 < NCT) {
