@@ -60,8 +60,8 @@ def level0_flops(m, n, b, form_q):
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py: this build runs on exactly one GPU (--gpus 1); the multi-GPU sharding "
-              "of the row blocks is described in DESIGN.md but not built", file=sys.stderr)
+        print("bench.py: the library runs on exactly one GPU (--gpus 1); sharding the row blocks "
+              "over several GPUs is not implemented", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1301_1071_amd as tsqr
