@@ -6,25 +6,29 @@ namespace {
 
 using namespace mfmaapply;
 
-// One work-group per (panel, 16 NT-column slice).  The 1-D grid keeps the ny slices of one
-// panel on the same XCD (work-group b runs on XCD b % 8): b = 8 ny g + 8 y + x covers panel
-// 8 g + x, slice y, so a panel's Q1 rows are read from HBM once and served from that XCD's L2
-// to the other slices.
+// One work-group per (panel, 16 NT-column slice, row chunk).  The 1-D grid keeps the ny * nrc
+// slices of one panel on the same XCD (work-group b runs on XCD b % 8): b = 8 S g + 8 s + x with
+// S = ny nrc covers panel 8 g + x, column slice s % ny and row chunk s / ny, so a panel's Q1 rows
+// are read from HBM once and served from that XCD's L2 to the other column slices.  Row chunks
+// (nrc > 1) only for launches with few panels, where one work-group per panel would leave most of
+// the chip idle and walk all of a panel's row blocks in turn.
 template <typename T, typename To, int NT>
 __global__ void __launch_bounds__(kWaves * 64)
 k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, int64_t ldq,
              const double *__restrict__ W, int64_t ldw, int64_t wstride, int k,
              To *__restrict__ out0, int64_t ld0, int k0, To *__restrict__ out1, int64_t ld1,
-             int accumulate, int64_t panels, int ny)
+             int accumulate, int64_t panels, int ny, int nrc)
 {
     const int64_t bid = blockIdx.x;
-    const int64_t grp = bid / (8 * ny);
-    const int rem = (int)(bid - grp * 8 * ny);
-    const int y = rem >> 3;
+    const int S = ny * nrc;
+    const int64_t grp = bid / (8 * S);
+    const int rem = (int)(bid - grp * 8 * S);
+    const int sl = rem >> 3;
+    const int y = sl % ny, rc = sl / ny;
     const int64_t p = grp * 8 + (rem & 7);
     if (p >= panels) return;
     apply_mfma_panel<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1,
-                                ld1, accumulate, p, y * 16 * NT);
+                                ld1, accumulate, p, y * 16 * NT, rc, nrc);
 }
 
 template <typename T, typename To, int NT>
@@ -43,10 +47,15 @@ hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t
     }
     const int64_t panels = ceil_div(rows, b);
     const int ny = (int)ceil_div(k, 16 * NT);
-    const int64_t blocks = ceil_div(panels, 8) * 8 * ny;
+    // row chunks: enough work-groups to cover the chip (2048), at most one 16-row block per wave
+    // and chunk round
+    const int max_chunks = (int)ceil_div(ceil_div(b, 16), kWaves);
+    const int64_t want = 2048 / (panels * ny);
+    const int nrc = (int)std::max<int64_t>(1, std::min<int64_t>(max_chunks, want));
+    const int64_t blocks = ceil_div(panels, 8) * 8 * ny * nrc;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kWaves * 64), lds, st, rows, (int)n, b,
                        (const T *)q1, ldq, W, ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1,
-                       ld1, acc, panels, ny);
+                       ld1, acc, panels, ny, nrc);
     return hipGetLastError();
 }
 

@@ -47,7 +47,7 @@ __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
                                                  const double *__restrict__ W, int64_t ldw,
                                                  int64_t wstride, int k, To *__restrict__ out0,
                                                  int64_t ld0, int k0, To *__restrict__ out1,
-                                                 int64_t ld1, int64_t p, int j0)
+                                                 int64_t ld1, int64_t p, int j0, int rc, int nrc)
 {
     typedef typename Mfma<T>::acc_t acc_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -107,7 +107,10 @@ __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
             }
         }
     }
-    if (w < nblk) fetch(w);
+    // this work-group's share of the panel's 16-row blocks: chunk rc of nrc, blocks dealt to the
+    // waves in turn
+    const int b0 = w + kWaves * rc, bstep = kWaves * nrc;
+    if (b0 < nblk) fetch(b0);
     // zero this wave's staging block once: columns [n, 4 KC) stay zero
     for (int e = lane; e < 16 * LDA; e += 64) as[e] = T(0);
     __syncthreads();
@@ -123,7 +126,7 @@ __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
         off0[i] = r * ld0 + jl;
         off1[i] = r * ld1 + jl - k0;
     }
-    for (int blk = w; blk < nblk; blk += kWaves) {
+    for (int blk = b0; blk < nblk; blk += bstep) {
         const int r0 = blk * 16;
         const int cnt = min(16, nr - r0);
         if (ok0) {
@@ -136,7 +139,7 @@ __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
                 for (int r = 0; r < 16; ++r) as[r * LDA + lane + 64] = pre2[r];
             }
         }
-        if (blk + kWaves < nblk) fetch(blk + kWaves);
+        if (blk + bstep < nblk) fetch(blk + bstep);
         // the wave reads back what its own lanes wrote: LDS operations of a wave are ordered
         acc_t acc[NT];
 #pragma unroll
@@ -177,11 +180,12 @@ __device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
                                                  const double *__restrict__ W, int64_t ldw,
                                                  int64_t wstride, int k, To *__restrict__ out0,
                                                  int64_t ld0, int k0, To *__restrict__ out1,
-                                                 int64_t ld1, int accumulate, int64_t p, int j0)
+                                                 int64_t ld1, int accumulate, int64_t p, int j0,
+                                                 int rc = 0, int nrc = 1)
 {
 #define TSQR_APPLY(ACC, WIDE)                                                                   \
     apply_panel_impl<T, To, NT, ACC, WIDE>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, \
-                                           k0, out1, ld1, p, j0)
+                                           k0, out1, ld1, p, j0, rc, nrc)
     if (n > 64) {
         if (accumulate) TSQR_APPLY(true, true);
         else TSQR_APPLY(false, true);
