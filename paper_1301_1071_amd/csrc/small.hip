@@ -14,9 +14,13 @@ namespace {
 constexpr int kSmallLdsLimit = 150 * 1024;
 
 // player at position `pos` of round `r` in the round-robin tournament of np players
+// (0 <= pos < np, 0 <= r < np - 1): player 0 stays, the others rotate by one place per round.
+// pos - 1 + r < 2 (np - 1), so one conditional subtraction is the reduction modulo np - 1.
 __device__ __forceinline__ int rr_player(int pos, int r, int np)
 {
-    return pos == 0 ? 0 : 1 + (pos - 1 + r) % (np - 1);
+    int x = pos - 1 + r;
+    if (x >= np - 1) x -= np - 1;
+    return pos == 0 ? 0 : 1 + x;
 }
 
 // reciprocal and reciprocal square root: hardware estimate plus two Newton steps (a few ulp)
