@@ -16,11 +16,15 @@
  *   - `ws` is a device workspace of at least tsqr_workspace_bytes(...) bytes; its contents on
  *     entry are ignored.
  *   - Argument errors are returned synchronously, before anything is enqueued.
- *   - Numerical conditions are reported through `d_info` (one device int32, written by the last
- *     kernel of the call; read it after synchronising the stream):
+ *   - Numerical conditions are reported through `d_info` (one device int32, written by the
+ *     kernels of the call; read it after synchronising the stream):
  *         0  success;
  *         j  (j > 0) R[j-1][j-1] == 0: A is rank deficient (the paper assumes full rank, Sec. I);
- *        -1  a non-finite value reached R (non-finite input).
+ *        -1  a non-finite value reached R (non-finite input);
+ *        -2  (TSQR_FP32_REFINED only) a Cholesky step of the refinement broke down: the FP32
+ *            R-hat does not precondition A (kappa(A) beyond about 1e14, or an R-hat that is
+ *            numerically singular in FP32); Q and R are then not valid;
+ *        -3  (adjoints only) the adjoint is undefined (zero pivot, repeated singular value).
  *   - The factorization is the unique thin QR with diag(R) > 0 (A full rank).  Q is m x n with
  *     orthonormal columns, R is n x n upper triangular (strict lower triangle written as 0).
  *   - Supported: 1 <= n <= TSQR_NMAX, m >= n.  Values must be well inside the floating-point
@@ -52,8 +56,8 @@ typedef enum {
  * always FP64. */
 typedef enum {
     TSQR_FP64 = 0,         /* everything FP64 */
-    TSQR_FP32_REFINED = 1, /* FP64 in/out: FP32 panels + FP32 Q1*Q2 GEMM, FP64 tree, then one FP64
-                              refinement pass that returns FP64 Q and R */
+    TSQR_FP32_REFINED = 1, /* FP64 in/out: R-hat from FP32 panels and the FP64 tree, then an FP64
+                              refinement against A that returns FP64 Q and R (see tsqr_qr) */
     TSQR_FP32 = 2          /* FP32 panels and GEMM, FP64 tree, no refinement */
 } tsqr_precision;
 
@@ -90,9 +94,14 @@ tsqr_status tsqr_r(int64_t m, int64_t n, const double *A, int64_t lda, double *R
 
 /*
  * Thin QR by direct TSQR (Sec. III-B steps 1-3): A (m x n, lda) = Q (m x n, ldq) R (n x n, ldr).
- * With opts->precision == TSQR_FP32_REFINED the panels and the Q1*Q2 GEMM run in FP32 and one
- * FP64 refinement pass (Y = A Rhat^{-1}, Y^T Y = Rc^T Rc, Q = Y Rc^{-1}, R = Rc Rhat) returns
- * FP64 results; TSQR_FP32 returns the unrefined FP32-path result in FP64 storage.
+ * TSQR_FP32 runs steps 1 and 3 (panels and the Q1*Q2 GEMM) in FP32 and returns that result in
+ * FP64 storage.  TSQR_FP32_REFINED (n <= 64) takes R-hat from the FP32 panels and FP64 tree and
+ * refines against A in FP64 (the indirect Q = A R^{-1} of Sec. II-B with the refinement of
+ * Sec. II-C): Y = A R-hat^{-1} by row-wise triangular solves, Y^T Y = Rc1^T Rc1,
+ * Q = Y Rc1^{-1}, R = Rc1 R-hat, with a second Cholesky pass (Rc2) decided on the device when
+ * ||Y^T Y - I||_F > 1/2.  A is read two or three times; no m x n intermediate is stored.  The
+ * backward error stays O(u) for any kappa(A); orthogonality holds to O(u) up to kappa(A) about
+ * 1e14, beyond which d_info may report -2.
  */
 tsqr_status tsqr_qr(int64_t m, int64_t n, const double *A, int64_t lda, double *Q, int64_t ldq,
                     double *R, int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
@@ -103,19 +112,31 @@ tsqr_status tsqr_qr(int64_t m, int64_t n, const double *A, int64_t lda, double *
  * in the same pass as Q (U_R is passed to step 3).  U: m x n (ldu); S: n values, descending;
  * V: n x n (ldv).  Gauge: each (u_k, v_k) pair is signed so that the largest-magnitude entry of
  * v_k (lowest index on ties) is positive.  Q (ldq) and R (ldr) are optional (NULL = not wanted).
+ * TSQR_FP32 runs the FP32 panels and product; TSQR_FP32_REFINED refines Q and R as tsqr_qr does,
+ * then takes the SVD of the refined R and U = Q U_R (one more product).  The workspace query
+ * (TSQR_OP_SVD) covers both the call with and without Q.
  */
 tsqr_status tsqr_svd(int64_t m, int64_t n, const double *A, int64_t lda, double *U, int64_t ldu,
                      double *S, double *V, int64_t ldv, double *Q, int64_t ldq, double *R,
                      int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
                      const tsqr_opts *opts, void *stream);
 
-/* FP32 input/output twins: FP32 panels and GEMM, FP64 tree and SVD (opts->precision ignored). */
+/* FP32 input/output twins: FP32 panels and GEMM, FP64 tree and SVD of R.  opts->precision
+ * may be TSQR_FP64 or TSQR_FP32 (both run this path; the workspace query with TSQR_FP32 gives the
+ * size); TSQR_FP32_REFINED returns TSQR_ERR_UNSUPPORTED (the refinement needs FP64 input). */
 tsqr_status tsqr_r_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *R, int64_t ldr,
                        void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
                        void *stream);
 tsqr_status tsqr_qr_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *Q, int64_t ldq,
                         float *R, int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
                         const tsqr_opts *opts, void *stream);
+/* SVD variant of Sec. III-B on FP32 data: FP32 panels and step-3 product (Q and U = Q U_R in one
+ * pass), FP64 tree and FP64 one-sided Jacobi SVD of R; S, V (and the optional Q, R) are written in
+ * FP32 with the conventions of tsqr_svd. */
+tsqr_status tsqr_svd_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *U, int64_t ldu,
+                         float *S, float *V, int64_t ldv, float *Q, int64_t ldq, float *R,
+                         int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                         const tsqr_opts *opts, void *stream);
 
 /*
  * Differentiation form: adjoint of tsqr_qr.  For the loss <dQ, Q> + <dR, R> with cotangents dQ
@@ -192,12 +213,12 @@ tsqr_status tsqr_qr_batched(tsqr_batch_plan plan, const void *const *d_A, void *
 
 /*
  * Panel-height table used by batched plans, one entry per (dtype, width class n <= 4, 8, 16,
- * 32, 64).  Each class has up to three panel variants: in FP64 (blocked panels) 0 = default
- * height, 1 = half height, 2 = 512 rows (n <= 16 only); in FP32 (register panels) 0 = default,
- * 1 and 2 = half height with half the rows per lane or half the waves.  tsqr_tune_variants lists
- * their heights for width n (0 = not usable: a panel must hold at least 3n rows, or the variant
- * repeats the default).  The autotuner (paper_1301_1071_amd/autotune.py) times them and records
- * its choice with tsqr_tune_set.  Set the table before creating plans; it is process-wide.
+ * 32, 64).  Each class has up to three variants of the blocked panel kernel, the same heights
+ * for FP64 and FP32: 0 = default (384 rows for n <= 32, 256 above), 1 = half the row tiles per
+ * wave (half height), 2 = 512 rows (n <= 16 only).  tsqr_tune_variants lists their heights for
+ * width n (0 = not usable: a panel must hold at least 3n rows, or the variant repeats the
+ * default).  The autotuner (paper_1301_1071_amd/autotune.py) times them and records its choice
+ * with tsqr_tune_set.  Set the table before creating plans; it is process-wide.
  */
 tsqr_status tsqr_tune_set(int32_t dtype, int64_t n, int32_t variant);
 tsqr_status tsqr_tune_get(int32_t dtype, int64_t n, int32_t *variant, int32_t *panel_rows);
@@ -222,9 +243,27 @@ tsqr_status tsqr_plan_levels(int32_t op, int64_t m, int64_t n, const tsqr_opts *
  * into ms[c] / launches[c] (host arrays), and clears the record.
  */
 tsqr_status tsqr_profile_enable(int32_t on);
+/* Record only the kernel classes whose bit is set in `mask` (bit c = class c; default: all), so
+ * that a timed region can be measured with events around one class only. */
+tsqr_status tsqr_profile_set_mask(uint32_t mask);
 tsqr_status tsqr_profile_collect(double *ms, int64_t *launches, int32_t nclasses);
 int32_t tsqr_profile_num_classes(void);
 const char *tsqr_profile_class_name(int32_t c);
+
+/* ------------------------------------------------------------------------------------------
+ * Error metrics of Sec. I-B (measurement, not part of the factorization).  Compensated Gram
+ * matrices over the m rows, accumulated in double-double (TwoProd by FMA and TwoSum, Ogita, Rump
+ * & Oishi 2005), so that ||Q^T Q - I|| is not swamped by the O(m u) rounding of an FP64 sum:
+ *   mode 0: G = X^T X - I;  mode 1: G = E^T E with E = A - X B (B n x n, each entry of E a
+ *   compensated dot product);  mode 2: G = X^T X.
+ * X, A: m x n device matrices (row-major, ldx, lda); G: n x n device (ld n, symmetric).  The
+ * caller takes the 2-norm of the small G (||Q^T Q - I||_2 = ||G||_2 for mode 0,
+ * ||A - QR||_2 = sqrt(lambda_max(G)) for mode 1).  ws: tsqr_metric_workspace_bytes.
+ * ------------------------------------------------------------------------------------------ */
+tsqr_status tsqr_metric_workspace_bytes(int64_t m, int64_t n, size_t *bytes);
+tsqr_status tsqr_metric_gram(int32_t mode, int64_t m, int64_t n, const double *X, int64_t ldx,
+                             const double *A, int64_t lda, const double *B, int64_t ldb,
+                             double *G, void *ws, size_t ws_bytes, void *stream);
 
 /* Human-readable status name (static string). */
 const char *tsqr_status_string(tsqr_status status);

@@ -32,6 +32,8 @@ SIGNATURES = {
                            _vp]),
     "tsqr_svd": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
                         _vp, _sz, _vp, _vp, _vp]),
+    "tsqr_svd_f32": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp,
+                            _i64, _vp, _sz, _vp, _vp, _vp]),
     "tsqr_qr_backward": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz,
                                  _vp, _vp, _vp]),
     "tsqr_svd_backward": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp,
@@ -47,9 +49,13 @@ SIGNATURES = {
     "tsqr_plan_levels": (_i32, [_i32, _i64, _i64, _vp, _i32, ctypes.POINTER(_i32),
                                  ctypes.POINTER(_i64), ctypes.POINTER(_i32)]),
     "tsqr_profile_enable": (_i32, [_i32]),
+    "tsqr_profile_set_mask": (_i32, [ctypes.c_uint32]),
     "tsqr_profile_collect": (_i32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), _i32]),
     "tsqr_profile_num_classes": (_i32, []),
     "tsqr_profile_class_name": (ctypes.c_char_p, [_i32]),
+    "tsqr_metric_workspace_bytes": (_i32, [_i64, _i64, ctypes.POINTER(_sz)]),
+    "tsqr_metric_gram": (_i32, [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz,
+                                _vp]),
     "tsqr_status_string": (ctypes.c_char_p, [_i32]),
     "tsqr_abi_version": (_i32, []),
     "tsqr_last_error": (ctypes.c_char_p, []),
@@ -102,6 +108,19 @@ def check(status: int, where: str) -> None:
 
 def profile_enable(on: bool) -> None:
     check(lib().tsqr_profile_enable(1 if on else 0), "tsqr_profile_enable")
+
+
+def profile_set_mask(classes=None) -> None:
+    """Record only the named kernel classes (None: all)."""
+    if classes is None:
+        mask = 0xFFFFFFFF
+    else:
+        n = lib().tsqr_profile_num_classes()
+        names = [lib().tsqr_profile_class_name(i).decode() for i in range(n)]
+        mask = 0
+        for c in classes:
+            mask |= 1 << names.index(c)
+    check(lib().tsqr_profile_set_mask(mask), "tsqr_profile_set_mask")
 
 
 def profile_collect() -> dict:

@@ -7,9 +7,11 @@
 //   finalize       R = D R~ (+ SVD of R), W_top = [D | D U_R], info;
 //   level T .. 0   apply:   Q1_p * W_p, W_p = rows [p n, p n + n) of the level above (the
 //                  reduce task's k-th key <-> rows (k-1)n+1..kn of its Q, Sec. III-B).
+#include <map>
 #include <mutex>
 #include <stdio.h>
 #include <string.h>
+#include <utility>
 #include <vector>
 
 #include "tsqr_internal.h"
@@ -24,6 +26,7 @@ struct ProfRec { int cls; hipEvent_t a, b; };
 struct Profiler {
     std::mutex mu;
     bool on = false;
+    uint32_t mask = 0xffffffffu;    // kernel classes recorded while on
     std::vector<hipEvent_t> pool;
     std::vector<ProfRec> recs;
     size_t next = 0;
@@ -36,6 +39,22 @@ void set_last_error(hipError_t e, const char *what, int line)
 {
     snprintf(g_last_error, sizeof(g_last_error), "%s (%d) in %.300s [line %d]",
              hipGetErrorString(e), (int)e, what, line);
+}
+
+hipError_t ensure_dynamic_lds(const void *kernel, size_t bytes)
+{
+    if (bytes <= 64 * 1024) return hipSuccess;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, size_t> granted;
+    std::lock_guard<std::mutex> lk(mu);
+    size_t &cur = granted[std::make_pair(kernel, dev)];
+    if (cur >= bytes) return hipSuccess;
+    e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) cur = bytes;
+    return e;
 }
 
 namespace {
@@ -82,12 +101,18 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
     pl.n = n;
     pl.in_dtype = in_dtype;
     pl.precision = o ? o->precision : TSQR_FP64;
-    if (in_dtype == F32) pl.precision = TSQR_FP32;
+    if (in_dtype == F32) {
+        // FP32 input always runs the FP32 path; a refinement needs FP64 input
+        if (pl.precision == TSQR_FP32_REFINED) return TSQR_ERR_UNSUPPORTED;
+        pl.precision = TSQR_FP32;
+    }
     if (pl.precision == TSQR_FP32_REFINED && n > 64) return TSQR_ERR_UNSUPPORTED;
     const int dtype0 = (pl.precision == TSQR_FP64) ? F64 : F32;
-    const bool refined = (pl.precision == TSQR_FP32_REFINED) && in_dtype == F64 && op == OP_QR;
+    // the refined precision form keeps only R-hat from the FP32 tree (steps 1-2), then refines
+    // against A; the SVD variant adds the SVD of the refined R and U = Q U_R
+    const bool refined = (pl.precision == TSQR_FP32_REFINED) && op != OP_R;
     const bool need_q = (op != OP_R) && !refined;
-    pl.k = need_q ? (int)((want_q ? n : 0) + (want_u ? n : 0)) : 0;
+    pl.k = need_q ? (int)((want_q ? n : 0) + (want_u ? n : 0)) : (refined && op == OP_SVD ? (int)n : 0);
 
     size_t off = kAlign;   // offset 0 is reserved so that 0 means "not allocated"
     auto take = [&](size_t bytes) {
@@ -105,11 +130,10 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         const int bl = lds_panel_rows_max(n, lv.dtype);
         const int breg = reg_panel_rows(n, lv.dtype);
         // levels run the blocked kernel, whose panels always shrink a stack of more than one
-        // panel (b >= 2n); short FP32 stacks and FP32 panels wider than 64 columns use one LDS
-        // (or global-memory) panel instead
+        // panel (b >= 2n); a short FP32 stack that they would not shrink uses one LDS (or
+        // global-memory) panel instead
         const bool shrinks = ceil_div(rows, breg) * n < rows;
-        const bool blk_ok = !(lv.dtype == F32 && n > 64);    // FP32 blocked panels: n <= 64
-        if (req == 0 && blk_ok && (rows <= breg || (shrinks && (lv.dtype == F64 || rows > 8 * n)))) {
+        if (req == 0 && (rows <= breg || (shrinks && (lv.dtype == F64 || rows > 8 * n)))) {
             // default: register-resident panels of the register kernel's height
             lv.reg = true;
             lv.global = false;
@@ -135,15 +159,16 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         if (lv.panels == 1) break;
         rows = lv.panels * n;
     }
-    if (need_q) pl.wtop = take(sizeof(double) * (size_t)n * pl.k);
+    if (pl.k) pl.wtop = take(sizeof(double) * (size_t)n * pl.k);
     if (op == OP_SVD) {
         pl.svd_g = take(sizeof(double) * (size_t)n * n);
         pl.svd_v = take(sizeof(double) * (size_t)n * n);
     }
     if (refined) {
-        pl.refine_blocks = refine_blocks(m, n);
         pl.refine = take(refine_scratch_bytes(m, n));
-        pl.svd_g = take(sizeof(double) * (size_t)n * n);   // Rhat
+        pl.rhat = take(sizeof(double) * (size_t)n * n);
+        pl.rref = take(sizeof(double) * (size_t)n * n);
+        if (op == OP_SVD && !want_q) pl.qtmp = take(sizeof(double) * (size_t)m * n);
     }
     pl.total = off;
     return TSQR_OK;
@@ -227,7 +252,27 @@ tsqr_status do_r(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda,
     const Level &top = pl.lev[pl.nlev - 1];
     ProfScope ps(PC_FINALIZE, st);
     TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), R, Rf, ldr, nullptr, 0, 0,
-                                   0, nullptr, nullptr, 0, nullptr, nullptr, d_info, st));
+                                   0, nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
+                                   d_info, st));
+    return TSQR_OK;
+}
+
+// The precision form's refinement (after the FP32 steps 1-2): R-hat = D R~ from the FP64 tree,
+// then the FP64 refinement writing Q (ldq) and R (ldr).
+tsqr_status run_refined(const Plan &pl, const double *A, int64_t lda, double *Q, int64_t ldq,
+                        double *R, int64_t ldr, void *ws, int32_t *d_info, hipStream_t st)
+{
+    const Level &top = pl.lev[pl.nlev - 1];
+    double *Rhat = (double *)wsp(ws, pl.rhat);
+    {
+        ProfScope ps(PC_FINALIZE, st);
+        TSQR_HIP_CHECK(launch_finalize(pl.n, (const double *)wsp(ws, top.s), Rhat, nullptr, pl.n,
+                                       nullptr, 0, 0, 0, nullptr, nullptr, nullptr, nullptr, 0,
+                                       nullptr, nullptr, d_info, st));
+    }
+    ProfScope ps(PC_REFINE, st);
+    TSQR_HIP_CHECK(launch_refine(pl.m, pl.n, A, lda, Rhat, Q, ldq, R, ldr, wsp(ws, pl.refine),
+                                 d_info, st));
     return TSQR_OK;
 }
 
@@ -246,27 +291,71 @@ tsqr_status do_qr(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda
     hipStream_t st = (hipStream_t)stream;
     if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
     const Level &top = pl.lev[pl.nlev - 1];
-    if (pl.k == 0) {
-        // precision form with refinement: Rhat from the FP32 path, then the FP64 pass
-        double *Rhat = (double *)wsp(ws, pl.svd_g);
-        {
-            ProfScope ps(PC_FINALIZE, st);
-            TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), Rhat, nullptr, n,
-                                           nullptr, 0, 0, 0, nullptr, nullptr, 0, nullptr,
-                                           nullptr, d_info, st));
-        }
-        ProfScope ps(PC_REFINE, st);
-        TSQR_HIP_CHECK(launch_refine(m, n, (const double *)A, lda, Rhat, (double *)Q, ldq, R, ldr,
-                                     wsp(ws, pl.refine), d_info, st));
-        return TSQR_OK;
-    }
+    if (pl.rhat)   // precision form with refinement
+        return run_refined(pl, (const double *)A, lda, (double *)Q, ldq, R, ldr, ws, d_info, st);
     {
         ProfScope ps(PC_FINALIZE, st);
         TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), R, Rf, ldr,
                                        (double *)wsp(ws, pl.wtop), pl.k, 1, 0, nullptr, nullptr,
-                                       0, nullptr, nullptr, d_info, st));
+                                       nullptr, nullptr, 0, nullptr, nullptr, d_info, st));
     }
     return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, nullptr, 0, st);
+}
+
+// Thin SVD (Sec. III-B, SVD paragraph): R = U_R S V^T at the top of the tree, U_R carried down
+// so that U = Q1 Q2 U_R comes out of step 3 with Q.  The refined precision form refines Q and R
+// first, then takes the SVD of the refined R and forms U = Q U_R with one more product.
+tsqr_status do_svd(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda, void *U,
+                   int64_t ldu, void *S, void *V, int64_t ldv, void *Q, int64_t ldq, void *R,
+                   int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
+                   void *stream)
+{
+    if (!A || !U || !S || !V || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldu < n || ldv < n || (Q && ldq < n) || (R && ldr < n))
+        return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    const tsqr_opts *o = opts_or_default(opts, tmp);
+    Plan pl;
+    const bool want_q = Q != nullptr;
+    tsqr_status s = build_plan(OP_SVD, m, n, in_dtype, o, want_q, true, pl);
+    if (s != TSQR_OK) return s;
+    if ((s = check_ws(pl, ws, ws_bytes)) != TSQR_OK) return s;
+    hipStream_t st = (hipStream_t)stream;
+    const bool f32 = in_dtype == F32;
+    if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
+    if (pl.rhat) {
+        // refined: Q (caller's or workspace) and R in FP64, then the SVD of R and U = Q U_R
+        double *Qd = want_q ? (double *)Q : (double *)wsp(ws, pl.qtmp);
+        const int64_t ldqd = want_q ? ldq : n;
+        double *Rr = (double *)wsp(ws, pl.rref);
+        if ((s = run_refined(pl, (const double *)A, lda, Qd, ldqd, Rr, n, ws, d_info, st)) != TSQR_OK)
+            return s;
+        {
+            ProfScope ps(PC_FINALIZE, st);
+            TSQR_HIP_CHECK(launch_finalize(n, Rr, (double *)R, nullptr, ldr,
+                                           (double *)wsp(ws, pl.wtop), pl.k, 0, 1, (double *)S,
+                                           nullptr, (double *)V, nullptr, ldv,
+                                           (double *)wsp(ws, pl.svd_g), (double *)wsp(ws, pl.svd_v),
+                                           d_info, st, 1));
+        }
+        ProfScope ps(PC_APPLY0, st);
+        TSQR_HIP_CHECK(launch_gemm_mfma(F64, F64, m, n, 256, Qd, ldqd, (const double *)wsp(ws, pl.wtop),
+                                        n, 0, (int)n, U, ldu, (int)n, nullptr, 0, 0, st));
+        return TSQR_OK;
+    }
+    const Level &top = pl.lev[pl.nlev - 1];
+    {
+        ProfScope ps(PC_FINALIZE, st);
+        TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s),
+                                       f32 ? nullptr : (double *)R, f32 ? (float *)R : nullptr, ldr,
+                                       (double *)wsp(ws, pl.wtop), pl.k, want_q ? 1 : 0, 1,
+                                       f32 ? nullptr : (double *)S, f32 ? (float *)S : nullptr,
+                                       f32 ? nullptr : (double *)V, f32 ? (float *)V : nullptr, ldv,
+                                       (double *)wsp(ws, pl.svd_g), (double *)wsp(ws, pl.svd_v),
+                                       d_info, st));
+    }
+    if (want_q) return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, U, ldu, st);
+    return run_apply_levels(pl, ws, in_dtype, U, ldu, (int)n, nullptr, 0, st);
 }
 
 // Backward workspace: the forward plan's workspace, then the recomputed factor and the adjoint
@@ -308,10 +397,10 @@ constexpr int kBwdPanel = 256;   // rows per work-group of the backward's tall p
 
 ProfScope::ProfScope(int c, hipStream_t s) : cls(c), st(s)
 {
-    if (!g_prof.on) return;
+    if (!g_prof.on || !((g_prof.mask >> c) & 1u)) return;
     std::lock_guard<std::mutex> lk(g_prof.mu);
     a = prof_event();
-    if (a) hipEventRecord(a, st);
+    if (a) (void)hipEventRecord(a, st);
 }
 
 ProfScope::~ProfScope()
@@ -320,7 +409,7 @@ ProfScope::~ProfScope()
     std::lock_guard<std::mutex> lk(g_prof.mu);
     hipEvent_t b = prof_event();
     if (!b) return;
-    hipEventRecord(b, st);
+    (void)hipEventRecord(b, st);
     g_prof.recs.push_back({cls, a, b});
 }
 
@@ -351,7 +440,15 @@ tsqr_status tsqr_workspace_bytes(int32_t op, int64_t m, int64_t n, const tsqr_op
     switch (op) {
     case TSQR_OP_R: s = build_plan(OP_R, m, n, F64, o, false, false, pl); break;
     case TSQR_OP_QR: s = build_plan(OP_QR, m, n, F64, o, true, false, pl); break;
-    case TSQR_OP_SVD: s = build_plan(OP_SVD, m, n, F64, o, true, true, pl); break;
+    case TSQR_OP_SVD: {
+        // the larger of the layouts with and without a Q output
+        Plan p2;
+        s = build_plan(OP_SVD, m, n, F64, o, true, true, pl);
+        if (s == TSQR_OK && build_plan(OP_SVD, m, n, F64, o, false, true, p2) == TSQR_OK &&
+            p2.total > pl.total)
+            pl.total = p2.total;
+        break;
+    }
     case TSQR_OP_QR_BACKWARD:
     case TSQR_OP_SVD_BACKWARD: {
         BwdLayout bl;
@@ -399,29 +496,17 @@ tsqr_status tsqr_svd(int64_t m, int64_t n, const double *A, int64_t lda, double 
                      int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
                      const tsqr_opts *opts, void *stream)
 {
-    if (!A || !U || !S || !V || !d_info) return TSQR_ERR_INVALID_ARG;
-    if (lda < n || ldu < n || ldv < n || (Q && ldq < n) || (R && ldr < n))
-        return TSQR_ERR_INVALID_ARG;
-    tsqr_opts tmp;
-    const tsqr_opts *o = opts_or_default(opts, tmp);
-    if (o && o->precision == TSQR_FP32_REFINED) return TSQR_ERR_UNSUPPORTED;
-    Plan pl;
-    const bool want_q = Q != nullptr;
-    tsqr_status s = build_plan(OP_SVD, m, n, F64, o, want_q, true, pl);
-    if (s != TSQR_OK) return s;
-    if ((s = check_ws(pl, ws, ws_bytes)) != TSQR_OK) return s;
-    hipStream_t st = (hipStream_t)stream;
-    if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
-    const Level &top = pl.lev[pl.nlev - 1];
-    {
-        ProfScope ps(PC_FINALIZE, st);
-        TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, top.s), R, nullptr, ldr,
-                                       (double *)wsp(ws, pl.wtop), pl.k, want_q ? 1 : 0, 1, S, V,
-                                       ldv, (double *)wsp(ws, pl.svd_g),
-                                       (double *)wsp(ws, pl.svd_v), d_info, st));
-    }
-    if (want_q) return run_apply_levels(pl, ws, F64, Q, ldq, (int)n, U, ldu, st);
-    return run_apply_levels(pl, ws, F64, U, ldu, (int)n, nullptr, 0, st);
+    return do_svd(F64, m, n, A, lda, U, ldu, S, V, ldv, Q, ldq, R, ldr, ws, ws_bytes, d_info, opts,
+                  stream);
+}
+
+tsqr_status tsqr_svd_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *U, int64_t ldu,
+                         float *S, float *V, int64_t ldv, float *Q, int64_t ldq, float *R,
+                         int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
+                         const tsqr_opts *opts, void *stream)
+{
+    return do_svd(F32, m, n, A, lda, U, ldu, S, V, ldv, Q, ldq, R, ldr, ws, ws_bytes, d_info, opts,
+                  stream);
 }
 
 tsqr_status tsqr_plan_levels(int32_t op, int64_t m, int64_t n, const tsqr_opts *opts,
@@ -471,7 +556,8 @@ tsqr_status tsqr_qr_backward(int64_t m, int64_t n, const double *A, int64_t lda,
         ProfScope ps(PC_FINALIZE, st);
         TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, bl.fwd.lev[bl.fwd.nlev - 1].s), R,
                                        nullptr, n, (double *)wsp(ws, bl.fwd.wtop), bl.fwd.k, 1, 0,
-                                       nullptr, nullptr, 0, nullptr, nullptr, d_info, st));
+                                       nullptr, nullptr, nullptr, nullptr, 0, nullptr, nullptr,
+                                       d_info, st));
     }
     if ((s = run_apply_levels(bl.fwd, ws, F64, Q, n, (int)n, nullptr, 0, st)) != TSQR_OK) return s;
     if (dQ) {
@@ -515,7 +601,8 @@ tsqr_status tsqr_svd_backward(int64_t m, int64_t n, const double *A, int64_t lda
         ProfScope ps(PC_FINALIZE, st);
         TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, bl.fwd.lev[bl.fwd.nlev - 1].s),
                                        nullptr, nullptr, 0, (double *)wsp(ws, bl.fwd.wtop),
-                                       bl.fwd.k, 0, 1, S, V, n, (double *)wsp(ws, bl.fwd.svd_g),
+                                       bl.fwd.k, 0, 1, S, nullptr, V, nullptr, n,
+                                       (double *)wsp(ws, bl.fwd.svd_g),
                                        (double *)wsp(ws, bl.fwd.svd_v), d_info, st));
     }
     if ((s = run_apply_levels(bl.fwd, ws, F64, U, n, (int)n, nullptr, 0, st)) != TSQR_OK) return s;
@@ -560,6 +647,13 @@ tsqr_status tsqr_profile_enable(int32_t on)
 {
     std::lock_guard<std::mutex> lk(g_prof.mu);
     g_prof.on = on != 0;
+    return TSQR_OK;
+}
+
+tsqr_status tsqr_profile_set_mask(uint32_t mask)
+{
+    std::lock_guard<std::mutex> lk(g_prof.mu);
+    g_prof.mask = mask;
     return TSQR_OK;
 }
 

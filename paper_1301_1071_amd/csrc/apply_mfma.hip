@@ -38,13 +38,8 @@ hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t
 {
     const size_t lds = apply_lds_bytes<T, NT>(n);
     auto kern = k_apply_mfma<T, To, NT>;
-    static size_t attr_bytes = 0;
-    if (lds > 64 * 1024 && lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
+    hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
+    if (e != hipSuccess) return e;
     const int64_t panels = ceil_div(rows, b);
     const int ny = (int)ceil_div(k, 16 * NT);
     // row chunks: enough work-groups to cover the chip (2048), at most one 16-row block per wave

@@ -219,13 +219,8 @@ hipError_t apply_batched_nt(int64_t n, const ApplyTask *tasks, int nt, int64_t b
 {
     const size_t lds = mfmaapply::apply_lds_bytes<T, NT>(n);
     auto kern = k_apply_batched<T, To, NT>;
-    static size_t attr_bytes = 0;
-    if (lds > 64 * 1024 && lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
+    hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks),
                        dim3(mfmaapply::kWaves * 64), lds, st, tasks, nt, Q, ws);
     return hipGetLastError();

@@ -20,10 +20,10 @@ template <typename T> struct BlkShapeRows {
 
 }  // namespace
 
-// FP64 panels wider than 64 columns (panel_blk_wide*.hip, one translation unit per width class
-// so that the build compiles them in parallel)
-hipError_t factor_blk_wide(int nct, int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
-                           double *S, hipStream_t st);
+// Panels wider than 64 columns (panel_blk_wide*.hip, one translation unit per width class so
+// that the build compiles them in parallel)
+hipError_t factor_blk_wide(int nct, int in_dtype, int dtype, int64_t rows, int64_t n,
+                           const void *X, int64_t ldx, void *q1, double *S, hipStream_t st);
 
 namespace {
 using namespace blklaunch;
@@ -44,8 +44,7 @@ hipError_t factor_blk_dispatch(int64_t rows, int64_t n, const void *X, int64_t l
 
 int reg_panel_rows(int64_t n, int dtype)
 {
-    // FP32 panels wider than 64 columns use the LDS kernel (see build_plan)
-    if (n > 64) return 256;
+    if (n > 64) return blklaunch::BlkShape<double, 5>::B;   // every class above 64 columns
     if (dtype == F32) return BlkShapeRows<float>::rows(n);
     return BlkShapeRows<double>::rows(n);
 }
@@ -54,12 +53,10 @@ hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, c
                              int64_t ldx, void *q1, double *S, hipStream_t st)
 {
     if (n < 1 || n > 128) return hipErrorInvalidValue;
-    if (dtype == F64) {
-        if (in_dtype != F64) return hipErrorInvalidValue;
-        if (n > 64) return factor_blk_wide((int)((n + 15) / 16), rows, n, X, ldx, q1, S, st);
-        return factor_blk_dispatch<double, double>(rows, n, X, ldx, q1, S, st);
-    }
-    if (n > 64) return hipErrorInvalidValue;
+    if (dtype == F64 && in_dtype != F64) return hipErrorInvalidValue;
+    if (n > 64)
+        return factor_blk_wide((int)((n + 15) / 16), in_dtype, dtype, rows, n, X, ldx, q1, S, st);
+    if (dtype == F64) return factor_blk_dispatch<double, double>(rows, n, X, ldx, q1, S, st);
     if (in_dtype == F64) return factor_blk_dispatch<double, float>(rows, n, X, ldx, q1, S, st);
     return factor_blk_dispatch<float, float>(rows, n, X, ldx, q1, S, st);
 }

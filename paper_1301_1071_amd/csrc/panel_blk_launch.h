@@ -36,13 +36,8 @@ hipError_t factor_blk_launch(int64_t rows, int64_t n, const void *X, int64_t ldx
 {
     using C = BlkShape<T, NCT>;
     const int64_t panels = ceil_div(rows, C::B);
-    static bool attr_set = false;
-    if (C::LDS > 64 * 1024 && !attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_factor_blk<Tin, T, NCT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)C::LDS);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    hipError_t e = ensure_dynamic_lds((const void *)k_factor_blk<Tin, T, NCT>, C::LDS);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_factor_blk<Tin, T, NCT>), dim3((unsigned)panels), dim3(C::NW * 64),
                        C::LDS, st, rows, (int)n, (const Tin *)X, ldx, (T *)q1, S);
     return hipGetLastError();

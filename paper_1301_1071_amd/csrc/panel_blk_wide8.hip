@@ -1,12 +1,16 @@
-// FP64 blocked panels for 113 <= n <= 128 (one width class per translation unit).
+// Blocked panels for 113 <= n <= 128 (one width class per translation unit, so that the
+// build compiles the wide classes in parallel): FP64 panels, and FP32 panels on FP64 or FP32 input.
 #include "panel_blk_launch.h"
 
 namespace tsqr {
 
-hipError_t factor_blk_wide8(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
-                            double *S, hipStream_t st)
+hipError_t factor_blk_wide8(int in_dtype, int dtype, int64_t rows, int64_t n, const void *X,
+                            int64_t ldx, void *q1, double *S, hipStream_t st)
 {
-    return blklaunch::factor_blk_launch<double, double, 8>(rows, n, X, ldx, q1, S, st);
+    using namespace blklaunch;
+    if (dtype == F64) return factor_blk_launch<double, double, 8>(rows, n, X, ldx, q1, S, st);
+    if (in_dtype == F64) return factor_blk_launch<double, float, 8>(rows, n, X, ldx, q1, S, st);
+    return factor_blk_launch<float, float, 8>(rows, n, X, ldx, q1, S, st);
 }
 
 }  // namespace tsqr

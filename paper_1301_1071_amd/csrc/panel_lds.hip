@@ -51,8 +51,8 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
     const int bp = (int)min((int64_t)b, rows - prow0);   // rows of A in this panel
     const int re = max(bp, n);                            // rows processed (zero padded)
 
-    for (int e = tid; e < re * n; e += kThreads) {
-        const int i = e / n, c = e - i * n;
+    for (int64_t e = tid; e < (int64_t)re * n; e += kThreads) {
+        const int i = (int)(e / n), c = (int)(e - (int64_t)i * n);
         P[(size_t)c * ldp + i] = (i < bp) ? (T)X[(prow0 + i) * ldx + c] : T(0);
     }
     __syncthreads();
@@ -153,8 +153,8 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
         }
         __syncthreads();
     }
-    for (int e = tid; e < bp * n; e += kThreads) {
-        const int i = e / n, c = e - i * n;
+    for (int64_t e = tid; e < (int64_t)bp * n; e += kThreads) {
+        const int i = (int)(e / n), c = (int)(e - (int64_t)i * n);
         q1[(prow0 + i) * n + c] = P[(size_t)c * ldp + i];
     }
 }
@@ -175,13 +175,8 @@ hipError_t factor_impl(int64_t rows, int64_t n, int b, const void *X, int64_t ld
 {
     const size_t lds = gpanel ? 0 : lds_bytes<T>((int)n, b);
     auto kern = k_factor_lds<Tin, T>;
-    static size_t attr_bytes = 0;     // largest dynamic LDS size requested so far
-    if (lds > 64 * 1024 && lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)kern,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
+    hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
+    if (e != hipSuccess) return e;
     const int64_t panels = ceil_div(rows, b);
     hipLaunchKernelGGL(kern, dim3((unsigned)panels), dim3(kThreads), lds, st, rows, (int)n, b,
                        b + 1, nc_log2_for(n), (const Tin *)X, ldx, (T *)q1, S, (T *)gpanel);

@@ -63,8 +63,9 @@ __device__ __forceinline__ double group16_sum(double v)
 __global__ void __launch_bounds__(kSvdThreads)
 k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *__restrict__ Rf,
            int64_t ldr, double *__restrict__ Wtop, int k, int want_q, int want_u,
-           double *__restrict__ S, double *__restrict__ V, int64_t ldv, double *G, double *Vw,
-           int use_lds, int32_t *__restrict__ info)
+           double *__restrict__ S, float *__restrict__ Sf, double *__restrict__ V,
+           float *__restrict__ Vf, int64_t ldv, double *G, double *Vw, int use_lds,
+           int32_t *__restrict__ info, int keep_info)
 {
     extern __shared__ __align__(16) double sm[];
     __shared__ double d_s[kNmaxPad];
@@ -97,7 +98,7 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
     }
     const int kq = want_q ? n : 0;
 
-    if (want_u || S != nullptr) {
+    if (want_u || S != nullptr || Sf != nullptr) {
         double *gG = use_lds ? sm : G;                     // column-major n x n
         double *gV = use_lds ? sm + (size_t)n * n : Vw;
         // one-sided Jacobi on R^T (column r of R^T is row r of R): R^T J = G with orthogonal
@@ -192,42 +193,46 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
             }
             s_sg[o] = (gG[(int64_t)c * n + imax] < 0.0) ? -1.0 : 1.0;
             if (S) S[o] = s_sv[c];
+            if (Sf) Sf[o] = (float)s_sv[c];
         }
         __syncthreads();
         for (int e = tid; e < n * n; e += nth) {
             const int i = e / n, o = e - i * n;
             const int c = perm[o];
             const double s = s_sv[c];
-            if (V) V[(int64_t)i * ldv + o] = (s > 0.0) ? s_sg[o] * gG[(int64_t)c * n + i] / s : 0.0;
+            const double vio = (s > 0.0) ? s_sg[o] * gG[(int64_t)c * n + i] / s : 0.0;
+            if (V) V[(int64_t)i * ldv + o] = vio;
+            if (Vf) Vf[(int64_t)i * ldv + o] = (float)vio;
             if (want_u) Wtop[(int64_t)i * k + kq + o] = d_s[i] * s_sg[o] * gV[(int64_t)c * n + i];
         }
     }
-    if (tid == 0) *info = s_nonfinite ? -1 : (s_zero == 0x7fffffff ? 0 : s_zero + 1);
+    if (tid == 0) {
+        const int32_t code = s_nonfinite ? -1 : (s_zero == 0x7fffffff ? 0 : s_zero + 1);
+        // keep_info: an earlier kernel of the call may already have reported a condition
+        if (!keep_info || *info == 0) *info = code;
+    }
 }
 
 }  // namespace
 
 hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, int64_t ldr,
-                           double *Wtop, int k, int want_q, int want_u, double *S, double *V,
-                           int64_t ldv, double *G, double *Vw, int32_t *info, hipStream_t st)
+                           double *Wtop, int k, int want_q, int want_u, double *S, float *Sf,
+                           double *V, float *Vf, int64_t ldv, double *G, double *Vw,
+                           int32_t *info, hipStream_t st, int keep_info)
 {
-    const bool svd = want_u || S != nullptr;
+    const bool svd = want_u || S != nullptr || Sf != nullptr;
     const size_t need = svd ? 2 * sizeof(double) * (size_t)n * n : 0;
     const int use_lds = (svd && need <= (size_t)kSmallLdsLimit) ? 1 : 0;
     const size_t lds = use_lds ? need : 0;
-    static size_t attr_bytes = 0;
-    if (lds > 64 * 1024 && lds > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)k_finalize,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_bytes = lds;
-    }
+    hipError_t e = ensure_dynamic_lds((const void *)k_finalize, lds);
+    if (e != hipSuccess) return e;
     // one 16-lane group per column pair of a Jacobi round, whole waves, so that each round's
     // barrier waits only for waves that have work
     const int64_t pairs = (n + (n & 1)) / 2;
     const int threads = (int)std::min<int64_t>(kSvdThreads, std::max<int64_t>(64, (16 * pairs + 63) / 64 * 64));
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(threads), lds, st, (int)n, Rt, R,
-                       Rf, ldr, Wtop, k, want_q, want_u, S, V, ldv, G, Vw, use_lds, info);
+                       Rf, ldr, Wtop, k, want_q, want_u, S, Sf, V, Vf, ldv, G, Vw, use_lds, info,
+                       keep_info);
     return hipGetLastError();
 }
 

@@ -39,6 +39,11 @@ void set_last_error(hipError_t e, const char *what, int line);
         }                                                                                   \
     } while (0)
 
+// Raise `kernel`'s dynamic-LDS limit to at least `bytes` on the current device.  The attribute
+// is set once per (kernel, device, larger size) under a lock, so concurrent host threads and
+// several devices are safe.  A no-op at or below the 64 KiB default.
+hipError_t ensure_dynamic_lds(const void *kernel, size_t bytes);
+
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -70,8 +75,10 @@ struct Plan {
     int k = 0;            // columns carried down the tree (n for Q or U, 2n for Q and U)
     size_t wtop = 0;      // n x k FP64: [D | D U_R]
     size_t svd_g = 0, svd_v = 0;   // n x n FP64 scratch for the Jacobi SVD
-    size_t refine = 0;    // refinement scratch (Gram partials etc.)
-    int refine_blocks = 0;
+    size_t refine = 0;    // refinement scratch (padded triangles, Gram partials)
+    size_t qtmp = 0;      // m x n FP64 Q for an SVD of the precision form without a Q output
+    size_t rhat = 0;      // n x n FP64 R-hat of the FP32 path (precision form with refinement)
+    size_t rref = 0;      // n x n FP64 refined R (SVD of the precision form)
     size_t total = 0;
 };
 
@@ -126,14 +133,18 @@ hipError_t launch_svd_bwd_small(int64_t n, const double *S, const double *V, con
 // Top of the tree: R = D Rt (D = diag(sign(Rt_jj)), sign(0) = +1) written to R (FP64, ldr) or Rf
 // (FP32, ldr); W_top (n x k) = [D | D U_R] (Q columns first if want_q, then U columns if want_u);
 // the SVD of R (one-sided Jacobi) when want_u or S != nullptr.  Sets *info.
+// S / V (FP64) or Sf / Vf (FP32) receive the singular values and right singular vectors.
+// keep_info != 0 leaves a nonzero *info from an earlier kernel of the call in place.
 hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, int64_t ldr,
-                           double *Wtop, int k, int want_q, int want_u, double *S, double *V,
-                           int64_t ldv, double *G, double *Vw, int32_t *info, hipStream_t st);
+                           double *Wtop, int k, int want_q, int want_u, double *S, float *Sf,
+                           double *V, float *Vf, int64_t ldv, double *G, double *Vw,
+                           int32_t *info, hipStream_t st, int keep_info = 0);
 
 // ---- launchers (refine.hip) ----------------------------------------------------------------
-int refine_blocks(int64_t m, int64_t n);
+// One FP64 refinement of the precision form (n <= 64): Q (FP64, ldq) and R (FP64, ldr) from A
+// and the FP32-path R-hat (n x n, ld n, diag > 0); info = -2 when a Cholesky step breaks down.
 size_t refine_scratch_bytes(int64_t m, int64_t n);
-hipError_t launch_refine(int64_t m, int64_t n, const double *A, int64_t lda, double *Rhat,
+hipError_t launch_refine(int64_t m, int64_t n, const double *A, int64_t lda, const double *Rhat,
                          double *Q, int64_t ldq, double *R, int64_t ldr, void *scratch,
                          int32_t *info, hipStream_t st);
 

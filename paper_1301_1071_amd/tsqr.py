@@ -77,7 +77,8 @@ def r(A: torch.Tensor, panel_rows: int = 0, ws: torch.Tensor | None = None,
 
 
 def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
-       ws: torch.Tensor | None = None, out=None, check_info: bool = True):
+       ws: torch.Tensor | None = None, out=None, check_info: bool = True,
+       info: torch.Tensor | None = None):
     """Thin QR by direct TSQR: returns (Q, R).  precision in {"fp64", "fp32", "fp32_refined"}
     for FP64 input; FP32 input always runs the FP32 path."""
     _require_gpu_matrix(A, (torch.float64, torch.float32))
@@ -88,7 +89,8 @@ def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
         R = torch.empty((n, n), dtype=A.dtype, device=A.device)
     else:
         Q, R = out
-    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
     prec = "fp32" if f32 else precision
     o = make_opts(prec, panel_rows)
     if ws is None:
@@ -100,11 +102,15 @@ def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
     return Q, R
 
 
-def svd(A: torch.Tensor, want_qr: bool = False, panel_rows: int = 0,
-        ws: torch.Tensor | None = None, out=None, check_info: bool = True):
-    """Thin SVD by direct TSQR: returns (U, S, V) or (U, S, V, Q, R) with want_qr."""
-    _require_gpu_matrix(A)
+def svd(A: torch.Tensor, want_qr: bool = False, precision: str = "fp64", panel_rows: int = 0,
+        ws: torch.Tensor | None = None, out=None, check_info: bool = True,
+        info: torch.Tensor | None = None):
+    """Thin SVD by direct TSQR: returns (U, S, V) or (U, S, V, Q, R) with want_qr.  precision in
+    {"fp64", "fp32", "fp32_refined"} for FP64 input; FP32 input runs the FP32 path and returns
+    FP32 results."""
+    _require_gpu_matrix(A, (torch.float64, torch.float32))
     m, n = A.shape
+    f32 = A.dtype == torch.float32
     if out is None:
         U = torch.empty((m, n), dtype=A.dtype, device=A.device)
         S = torch.empty((n,), dtype=A.dtype, device=A.device)
@@ -113,22 +119,19 @@ def svd(A: torch.Tensor, want_qr: bool = False, panel_rows: int = 0,
         R = torch.empty((n, n), dtype=A.dtype, device=A.device) if want_qr else None
     else:
         U, S, V, Q, R = out
-    info = torch.zeros(1, dtype=torch.int32, device=A.device)
-    o = make_opts("fp64", panel_rows)
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    prec = "fp32" if f32 else precision
+    o = make_opts(prec, panel_rows)
     if ws is None:
-        nb = _svd_ws_bytes(m, n, want_qr, panel_rows)
-        ws = torch.empty(nb, dtype=torch.uint8, device=A.device)
-    check(lib().tsqr_svd(m, n, _p(A), A.stride(0), _p(U), U.stride(0), _p(S), _p(V), V.stride(0),
-                         _p(Q), Q.stride(0) if Q is not None else 0, _p(R),
-                         R.stride(0) if R is not None else 0, _p(ws), ws.numel(), _p(info),
-                         ctypes.byref(o), _stream(A.device)), "tsqr_svd")
+        ws = _workspace("svd", m, n, prec, panel_rows, A.device)
+    fn = lib().tsqr_svd_f32 if f32 else lib().tsqr_svd
+    check(fn(m, n, _p(A), A.stride(0), _p(U), U.stride(0), _p(S), _p(V), V.stride(0),
+             _p(Q), Q.stride(0) if Q is not None else 0, _p(R),
+             R.stride(0) if R is not None else 0, _p(ws), ws.numel(), _p(info),
+             ctypes.byref(o), _stream(A.device)), fn.__name__)
     _info_check(info, check_info, "tsqr_svd")
     return (U, S, V, Q, R) if want_qr else (U, S, V)
-
-
-def _svd_ws_bytes(m, n, want_qr, panel_rows):
-    # the workspace query reports the SVD plan with Q and U both carried (the larger case)
-    return workspace_bytes("svd", m, n, "fp64", panel_rows)
 
 
 def _cotangent(x, shape, A):
@@ -329,3 +332,44 @@ def tune_variants(dtype, n: int):
     c = ctypes.c_int32(0)
     check(lib().tsqr_tune_variants(_DTYPES[dtype], n, 8, buf, ctypes.byref(c)), "tsqr_tune_variants")
     return [int(buf[i]) for i in range(c.value)]
+
+
+# ----------------------------------------------------------------------------- error metrics
+def metric_gram(mode: int, X: torch.Tensor, A: torch.Tensor | None = None,
+                B: torch.Tensor | None = None) -> torch.Tensor:
+    """Compensated n x n Gram on the GPU (tsqr_metric_gram): mode 0 X^T X - I, mode 1
+    (A - X B)^T (A - X B), mode 2 X^T X.  FP64 GPU tensors; returns an n x n GPU tensor."""
+    _require_gpu_matrix(X)
+    m, n = X.shape
+    nb = ctypes.c_size_t(0)
+    check(lib().tsqr_metric_workspace_bytes(m, n, ctypes.byref(nb)), "tsqr_metric_workspace_bytes")
+    ws = torch.empty(int(nb.value), dtype=torch.uint8, device=X.device)
+    G = torch.empty((n, n), dtype=torch.float64, device=X.device)
+    if mode == 1:
+        _require_gpu_matrix(A)
+        B = B if B.stride(1) == 1 else B.contiguous()
+    check(lib().tsqr_metric_gram(mode, m, n, _p(X), X.stride(0), _p(A),
+                                 A.stride(0) if A is not None else 0, _p(B),
+                                 B.stride(0) if B is not None else 0, _p(G), _p(ws), ws.numel(),
+                                 _stream(X.device)), "tsqr_metric_gram")
+    return G
+
+
+def _sym_norm2(G: torch.Tensor) -> float:
+    import numpy as np
+    return float(np.max(np.abs(np.linalg.eigvalsh(G.cpu().numpy()))))
+
+
+def metric_orth(Q: torch.Tensor) -> float:
+    """||Q^T Q - I||_2 (Sec. I-B), compensated Gram on the GPU."""
+    return _sym_norm2(metric_gram(0, Q))
+
+
+def metric_norm2(A: torch.Tensor) -> float:
+    """||A||_2 = sqrt(lambda_max(A^T A))."""
+    return _sym_norm2(metric_gram(2, A)) ** 0.5
+
+
+def metric_residual(A: torch.Tensor, Q: torch.Tensor, B: torch.Tensor) -> float:
+    """||A - Q B||_2 with compensated residual rows."""
+    return _sym_norm2(metric_gram(1, Q, A, B)) ** 0.5

@@ -197,3 +197,61 @@ def test_tune_table_queries():
     v, rows = ctypes.c_int32(), ctypes.c_int32()
     assert L.tsqr_tune_get(1, 16, ctypes.byref(v), ctypes.byref(rows)) == 0
     assert rows.value > 0
+
+
+@pytest.mark.skipif(_gpu_visible(), reason="fake device pointers are only passed where no GPU exists")
+def test_new_entry_points_reject_bad_arguments_without_gpu():
+    """tsqr_svd_f32, the refined precision on FP32 entry points, and the metric Gram."""
+    L = lib()
+    info = FAKE
+    assert L.tsqr_svd_f32(100, 10, None, 10, FAKE, 10, FAKE, FAKE, 10, None, 0, None, 0, FAKE,
+                          1 << 30, info, None, None) == 1
+    assert L.tsqr_svd_f32(5, 10, FAKE, 10, FAKE, 10, FAKE, FAKE, 10, None, 0, None, 0, FAKE,
+                          1 << 30, info, None, None) == 2
+    assert L.tsqr_svd_f32(100, 10, FAKE, 10, FAKE, 10, FAKE, FAKE, 10, None, 0, None, 0, FAKE,
+                          16, info, None, None) == 3
+    # the refinement needs FP64 input: FP32 entry points reject it (the FP64 workspace query of
+    # the refined form would not cover the FP32 path)
+    ref = make_opts("fp32_refined")
+    for fn in (L.tsqr_qr_f32,):
+        assert fn(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, ctypes.byref(ref),
+                  None) == 4
+    assert L.tsqr_r_f32(100, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, ctypes.byref(ref),
+                        None) == 4
+    assert L.tsqr_svd_f32(100, 10, FAKE, 10, FAKE, 10, FAKE, FAKE, 10, None, 0, None, 0, FAKE,
+                          1 << 30, info, ctypes.byref(ref), None) == 4
+    # FP32 entry points accept the FP32 and FP64 precision codes alike
+    o32 = make_opts("fp32")
+    assert L.tsqr_qr_f32(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 16, info,
+                         ctypes.byref(o32), None) == 3
+    # metric Gram: bad mode, missing inputs, shape, workspace
+    G = FAKE
+    assert L.tsqr_metric_gram(3, 100, 10, FAKE, 10, None, 0, None, 0, G, FAKE, 1 << 30, None) == 1
+    assert L.tsqr_metric_gram(1, 100, 10, FAKE, 10, None, 0, FAKE, 10, G, FAKE, 1 << 30, None) == 1
+    assert L.tsqr_metric_gram(0, 100, 200, FAKE, 200, None, 0, None, 0, G, FAKE, 1 << 30, None) == 2
+    assert L.tsqr_metric_gram(0, 100, 10, FAKE, 10, None, 0, None, 0, G, FAKE, 8, None) == 3
+
+
+def test_fp32_wide_panels_are_blocked():
+    """FP32 panels wider than 64 columns run the blocked kernel with many panels (no single
+    m-row panel), and the recursion shrinks every level."""
+    from paper_1301_1071_amd._lib import plan_levels
+    lv = plan_levels("qr", 16_000_000, 100, "fp32")
+    assert len(lv) > 1
+    assert lv[0] == (16_000_000, 256)
+    for (rows, b), (rows_next, _) in zip(lv, lv[1:]):
+        assert rows_next == -(-rows // b) * 100 and rows_next < rows
+
+
+def test_svd_workspace_covers_both_outputs_and_refined_forms():
+    st, b = _ws("svd", 200_000, 25)
+    assert st == 0
+    st, bref = _ws("svd", 200_000, 25, make_opts("fp32_refined"))
+    assert st == 0 and bref >= 200_000 * 25 * 8         # holds Q when the caller gives none
+    st, bq = _ws("qr", 200_000, 25, make_opts("fp32_refined"))
+    assert st == 0 and bq < 200_000 * 25 * 8            # no m x n intermediate is stored
+    st, b32 = _ws("qr", 200_000, 25, make_opts("fp32"))
+    assert st == 0 and b32 < _ws("qr", 200_000, 25)[1]  # FP32 level-0 panels
+    nb = ctypes.c_size_t()
+    assert lib().tsqr_metric_workspace_bytes(1000, 10, ctypes.byref(nb)) == 0 and nb.value > 0
+    assert lib().tsqr_metric_workspace_bytes(1000, 129, ctypes.byref(nb)) == 2

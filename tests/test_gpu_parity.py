@@ -236,3 +236,104 @@ def test_repeated_calls_reuse_workspace_and_outputs():
             assert all(torch.equal(a, b) for a, b in zip(ref, cur))
     Q = outs[3].cpu().numpy()
     assert oracle.metric_orth(Q) <= 1e-12
+
+
+# --------------------------------------------------------------------- full-size workloads
+def test_svd_c50_full_size():
+    """svd-c50 at its full size (4,000,000 x 50, cond 1e12) against the oracle (blocks of
+    8,192 rows): R relative <= 1e-12, max |dS| / s1 <= 1e-12 and the backward-stable invariants
+    <= 1e-12 (Q and U forward errors scale with kappa(A) and are not gated here)."""
+    t = tsqr_mod()
+    A = workloads.config_matrix("svd-c50")
+    U, S, V, Q, R = (x.cpu().numpy() for x in t.svd(to_gpu(A), want_qr=True))
+    Uo, So, Vo, Qo, Ro = oracle.tsqr_svd(A, block_rows=8192, want_qr=True)
+    normA = So[0]
+    assert rel(R, Ro) <= 1e-12, rel(R, Ro)
+    assert np.abs(S - So).max() <= 1e-12 * So[0]
+    assert np.all(np.diag(R) > 0) and np.all(np.tril(R, -1) == 0)
+    assert oracle.metric_orth(Q) <= 1e-12
+    assert oracle.metric_backward(A, Q, R, normA) <= 1e-12
+    assert oracle.metric_svd_backward(A, U, S, V, normA) <= 1e-12
+    assert oracle.metric_orth(U) <= 1e-12
+    assert oracle.metric_orth(V) <= 1e-12
+
+
+def test_mixed_c25_full_size():
+    """mixed-c25 at its full size (16,000,000 x 25, cond 1e4): the FP32 form within 1e-5 of the
+    FP64 oracle before refinement, the refined form within 1e-12 after."""
+    t = tsqr_mod()
+    A = workloads.config_matrix("mixed-c25")
+    Ad = to_gpu(A)
+    Ro = oracle.tsqr(A, block_rows=8192, want_q=False)
+    normA = oracle.norm2(A)
+    Qf, Rf = (x.cpu().numpy() for x in t.qr(Ad, precision="fp32"))
+    assert rel(Rf, Ro) <= 1e-5
+    assert oracle.metric_orth(Qf) <= 1e-5
+    assert oracle.metric_backward(A, Qf, Rf, normA) <= 1e-5
+    del Qf
+    Qr, Rr = (x.cpu().numpy() for x in t.qr(Ad, precision="fp32_refined"))
+    assert rel(Rr, Ro) <= 1e-12
+    assert oracle.metric_orth(Qr) <= 1e-12
+    assert oracle.metric_backward(A, Qr, Rr, normA) <= 1e-12
+
+
+# --------------------------------------------------------------------- precision form extensions
+@pytest.mark.parametrize("log_cond", [8.0, 12.0])
+def test_refinement_ill_conditioned(log_cond):
+    """Beyond the FP32 range of kappa(A) the refinement's second Cholesky pass keeps the FP64
+    gates (R, orthogonality, backward error) at 1e-12."""
+    t = tsqr_mod()
+    A, s, _ = workloads.spectrum_matrix(200_000, 25, log_cond, seed=300 + int(log_cond))
+    Ro = oracle.tsqr(A, block_rows=8192, want_q=False)
+    Q, R = (x.cpu().numpy() for x in t.qr(to_gpu(A), precision="fp32_refined"))
+    normA = oracle.norm2(A)
+    assert oracle.metric_orth(Q) <= 1e-12
+    assert oracle.metric_backward(A, Q, R, normA) <= 1e-12
+    assert rel(R, Ro) <= 1e-12
+    assert np.all(np.diag(R) > 0)
+
+
+@pytest.mark.parametrize("want_qr", [False, True])
+def test_svd_precision_refined(want_qr):
+    t = tsqr_mod()
+    A, s, _ = workloads.spectrum_matrix(150_000, 25, 4.0, seed=77)
+    out = t.svd(to_gpu(A), want_qr=want_qr, precision="fp32_refined")
+    U, S, V = (x.cpu().numpy() for x in out[:3])
+    check_svd(A, U, S, V, tol_vec=None, block_rows=8192)
+    if want_qr:
+        Q, R = out[3].cpu().numpy(), out[4].cpu().numpy()
+        check_qr_fp64(A, Q, R, tol_q=None, block_rows=8192)
+
+
+@pytest.mark.parametrize("m,n", [(60_000, 10), (20_000, 50), (9000, 100)])
+def test_svd_f32_io(m, n):
+    t = tsqr_mod()
+    A32 = gauss(m, n, 500 + n).astype(np.float32)
+    A = A32.astype(np.float64)
+    U, S, V, Q, R = (x.cpu().numpy().astype(np.float64) for x in t.svd(to_gpu(A32), want_qr=True))
+    Uo, So, Vo = oracle.tsqr_svd(A, block_rows=1000)
+    assert np.abs(S - So).max() <= 1e-5 * So[0]
+    assert np.all(np.diff(S) <= 0)
+    assert oracle.metric_orth(U) <= 1e-5
+    assert oracle.metric_orth(V) <= 1e-5
+    assert oracle.metric_svd_backward(A, U, S, V) <= 1e-5
+    assert oracle.metric_backward(A, Q, R) <= 1e-5
+
+
+def test_gpu_metrics_match_oracle_metrics():
+    """The compensated GPU Gram metrics agree with the oracle's long-double metrics."""
+    t = tsqr_mod()
+    A = workloads.spectrum_matrix(300_000, 30, 6.0, seed=12)[0]
+    Ad = to_gpu(A)
+    Q, R = t.qr(Ad)
+    Qh, Rh = Q.cpu().numpy(), R.cpu().numpy()
+    o_gpu, o_cpu = t.metric_orth(Q), oracle.metric_orth(Qh)
+    assert abs(o_gpu - o_cpu) <= 0.05 * o_cpu + 1e-18
+    n_gpu, n_cpu = t.metric_norm2(Ad), oracle.norm2(A)
+    assert abs(n_gpu - n_cpu) <= 1e-12 * n_cpu
+    r_gpu, r_cpu = t.metric_residual(Ad, Q, R), oracle.residual(A, Qh, Rh)
+    assert abs(r_gpu - r_cpu) <= 0.05 * r_cpu + 1e-30
+    # a planted departure from orthogonality is seen at its size
+    Qp = Q.clone()
+    Qp[7, 3] += 1e-13
+    assert abs(t.metric_orth(Qp) - oracle.metric_orth(Qp.cpu().numpy())) <= 1e-15
