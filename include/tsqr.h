@@ -93,6 +93,21 @@ tsqr_status tsqr_r(int64_t m, int64_t n, const double *A, int64_t lda, double *R
                    void *stream);
 
 /*
+ * tsqr_r without a caller workspace, for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  The same kernels as
+ * tsqr_r (bit-identical R); the workspace is a fixed device array inside the library of
+ * TSQR_NOALLOC_SCRATCH_BYTES bytes per GPU, held from the first call on that GPU until the process
+ * ends.  The call itself allocates nothing.  Inputs whose tsqr_r workspace
+ * (tsqr_workspace_bytes(TSQR_OP_R, ...)) exceeds that size return TSQR_ERR_WORKSPACE before
+ * anything is enqueued (e.g. n = 50 up to about 3.4M rows, n = 10 up to about 60M rows).  Every
+ * call on one GPU shares the array: calls that overlap in time on one GPU (other streams, other
+ * host threads) race and must be serialised by the caller.  Nothing in it needs clearing.
+ */
+#define TSQR_NOALLOC_SCRATCH_BYTES (128ull << 20)
+tsqr_status tsqr_r_noalloc(int64_t m, int64_t n, const double *A, int64_t lda, double *R,
+                           int64_t ldr, int32_t *d_info, const tsqr_opts *opts, void *stream);
+
+/*
  * Thin QR by direct TSQR (Sec. III-B steps 1-3): A (m x n, lda) = Q (m x n, ldq) R (n x n, ldr).
  * TSQR_FP32 runs steps 1 and 3 (panels and the Q1*Q2 GEMM) in FP32 and returns that result in
  * FP64 storage.  TSQR_FP32_REFINED (n <= 64) takes R-hat from the FP32 panels and FP64 tree and

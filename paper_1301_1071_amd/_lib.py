@@ -27,6 +27,7 @@ SIGNATURES = {
     "tsqr_workspace_bytes": (_i32, [_i32, _i64, _i64, _vp, ctypes.POINTER(_sz)]),
     "tsqr_r": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
     "tsqr_r_f32": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
+    "tsqr_r_noalloc": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _vp]),
     "tsqr_qr": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
     "tsqr_qr_f32": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp,
                            _vp]),

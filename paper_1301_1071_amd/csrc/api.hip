@@ -393,6 +393,35 @@ tsqr_status build_bwd_layout(bool svd, int64_t m, int64_t n, const tsqr_opts *o,
 
 constexpr int kBwdPanel = 256;   // rows per work-group of the backward's tall products
 
+// Workspace of tsqr_r_noalloc: a fixed device array (each GPU that runs the library holds its
+// own copy until the process ends).  Host code never uses the array's name as an address: the
+// device address is taken once per device with hipGetSymbolAddress, with that device current.
+constexpr size_t kNoallocScratchBytes = (size_t)TSQR_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocScratchBytes];
+constexpr int kMaxDevices = 64;
+std::once_flag g_scratch_once[kMaxDevices];
+void *g_scratch_ptr[kMaxDevices];
+hipError_t g_scratch_err[kMaxDevices];
+
+// The current device's scratch address (set up on the first call on that device).
+void *device_scratch(hipError_t &err)
+{
+    int dev = 0;
+    err = hipGetDevice(&dev);
+    if (err != hipSuccess) return nullptr;
+    if (dev < 0 || dev >= kMaxDevices) {
+        err = hipErrorInvalidDevice;
+        return nullptr;
+    }
+    std::call_once(g_scratch_once[dev], [dev] {
+        void *p = nullptr;
+        g_scratch_err[dev] = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        g_scratch_ptr[dev] = (g_scratch_err[dev] == hipSuccess) ? p : nullptr;
+    });
+    err = g_scratch_err[dev];
+    return g_scratch_ptr[dev];
+}
+
 }  // namespace
 
 ProfScope::ProfScope(int c, hipStream_t s) : cls(c), st(s)
@@ -468,6 +497,25 @@ tsqr_status tsqr_r(int64_t m, int64_t n, const double *A, int64_t lda, double *R
                    void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts, void *stream)
 {
     return do_r(F64, m, n, A, lda, R, nullptr, ldr, ws, ws_bytes, d_info, opts, stream);
+}
+
+tsqr_status tsqr_r_noalloc(int64_t m, int64_t n, const double *A, int64_t lda, double *R,
+                           int64_t ldr, int32_t *d_info, const tsqr_opts *opts, void *stream)
+{
+    if (!A || !R || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldr < n) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    Plan pl;
+    tsqr_status s = build_plan(OP_R, m, n, F64, opts_or_default(opts, tmp), false, false, pl);
+    if (s != TSQR_OK) return s;
+    if (pl.total > kNoallocScratchBytes) return TSQR_ERR_WORKSPACE;
+    hipError_t e = hipSuccess;
+    void *ws = device_scratch(e);
+    if (e != hipSuccess) {
+        set_last_error(e, "hipGetSymbolAddress(scratch)", __LINE__);
+        return TSQR_ERR_HIP;
+    }
+    return do_r(F64, m, n, A, lda, R, nullptr, ldr, ws, kNoallocScratchBytes, d_info, opts, stream);
 }
 
 tsqr_status tsqr_r_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *R, int64_t ldr,
