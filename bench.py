@@ -20,7 +20,8 @@ Prints ONE JSON line:
   cpu_baseline          the CPU oracle on a bounded sample, on this host's cores;
   forms                 the other workloads on the same GPU: qr-small (graph replays),
                         mixed-c25 (FP64 vs FP32 vs FP32 + refinement), batch512 (FP64 / FP32,
-                        per width), grad-c100 (forward vs adjoint).
+                        per width), grad-c100 (forward vs adjoint), stability (Sec. IV:
+                        ||Q^T Q - I|| of direct TSQR and the comparison methods per condition).
 """
 from __future__ import annotations
 
@@ -346,7 +347,7 @@ def main():
 # ----------------------------------------------------------------------------- the other forms
 def bench_forms(args, dev):
     out = {}
-    for fn in (form_qr_small, form_mixed, form_batched, form_grad):
+    for fn in (form_qr_small, form_mixed, form_batched, form_grad, form_stability):
         t0 = time.perf_counter()
         try:
             out[fn.__name__[5:]] = fn(args, dev)
@@ -510,6 +511,38 @@ def form_grad(args, dev):
     res["qr_forward_GBps"] = 16.0 * m * n / (res["qr_forward_ms"] * 1e-3) / 1e9
     res["dA_finite"] = bool(torch.isfinite(dA).all())
     return res
+
+
+def form_stability(args, dev):
+    """The stability experiment of Sec. IV on the GPU: ||Q^T Q - I||_2 and the backward error of
+    direct TSQR and the comparison methods (Cholesky QR, indirect TSQR with Q = A R^{-1}, each
+    with and without one step of iterative refinement) on 100,000 x 10 matrices
+    A = G diag(logspace(0, -c, 10)) V^T, c = 0, 2, ..., 16.  A method that breaks down (Cholesky
+    of a Gram matrix that is not numerically positive definite) is reported as "breakdown"."""
+    import torch
+    import paper_1301_1071_amd as tsqr
+    import workloads
+    m, n = 100_000, 10
+    rows = {}
+    for c in range(0, 17, 2):
+        A = torch.from_numpy(workloads.spectrum_matrix(m, n, float(c), seed=700 + c)[0]).to(dev)
+        normA = tsqr.metric_norm2(A)
+        r = {}
+        Q, R = tsqr.qr(A, check_info=False)
+        r["direct"] = {"orth": tsqr.metric_orth(Q), "backward": tsqr.metric_residual(A, Q, R) / normA,
+                       "ms": wall_ms(lambda: tsqr.qr(A, out=(Q, R), check_info=False), 5, 1)}
+        for meth in ("cholqr", "cholqr_ir", "indirect", "indirect_ir"):
+            Q, R, info = tsqr.qr_indirect(A, meth)
+            ms = wall_ms(lambda: tsqr.qr_indirect(A, meth, out=(Q, R)), 5, 1)
+            Q, R, info = tsqr.qr_indirect(A, meth, out=(Q, R))
+            torch.cuda.synchronize()
+            if int(info.item()) == -4:
+                r[meth] = {"orth": "breakdown", "backward": None, "ms": ms}
+            else:
+                r[meth] = {"orth": tsqr.metric_orth(Q),
+                           "backward": tsqr.metric_residual(A, Q, R) / normA, "ms": ms}
+        rows["1e%d" % c] = r
+    return {"m": m, "n": n, "by_cond": rows}
 
 
 # ----------------------------------------------------------------------------- CPU baseline

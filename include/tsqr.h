@@ -24,7 +24,8 @@
  *        -2  (TSQR_FP32_REFINED only) a Cholesky step of the refinement broke down: the FP32
  *            R-hat does not precondition A (kappa(A) beyond about 1e14, or an R-hat that is
  *            numerically singular in FP32); Q and R are then not valid;
- *        -3  (adjoints only) the adjoint is undefined (zero pivot, repeated singular value).
+ *        -3  (adjoints only) the adjoint is undefined (zero pivot, repeated singular value);
+ *        -4  (Cholesky QR only) A^T A is not numerically positive definite.
  *   - The factorization is the unique thin QR with diag(R) > 0 (A full rank).  Q is m x n with
  *     orthonormal columns, R is n x n upper triangular (strict lower triangle written as 0).
  *   - Supported: 1 <= n <= TSQR_NMAX, m >= n.  Values must be well inside the floating-point
@@ -264,6 +265,26 @@ tsqr_status tsqr_profile_set_mask(uint32_t mask);
 tsqr_status tsqr_profile_collect(double *ms, int64_t *launches, int32_t nclasses);
 int32_t tsqr_profile_num_classes(void);
 const char *tsqr_profile_class_name(int32_t c);
+
+/* ------------------------------------------------------------------------------------------
+ * Comparison methods of the stability experiment (Sec. IV), not direct TSQR: they exist so that
+ * the experiment can run beside tsqr_qr on the same GPU.
+ *   TSQR_METHOD_CHOLQR    Cholesky QR (Sec. II-A): R^T R = A^T A, the Gram summed over row blocks
+ *                         (Alg. 1) and factored by Cholesky; fails when A^T A is not numerically
+ *                         positive definite (d_info = -4; Q and R are then not valid).
+ *   TSQR_METHOD_INDIRECT  indirect TSQR (Sec. II-B): R from the stacked-R reduction alone.
+ * Both form Q = A R^{-1} with the explicit inverse of R (Sec. II-C), which is not backward
+ * stable: ||Q^T Q - I|| grows with kappa(A) (Cholesky QR: with kappa(A)^2).  refine = 1 repeats
+ * the same QR once on the computed Q (iterative refinement, Sec. I): Q = Q1 R2^{-1}, R = R2 R1.
+ * FP64 only (opts->precision must be TSQR_FP64).  A, Q: m x n; R: n x n upper triangular.
+ * ------------------------------------------------------------------------------------------ */
+typedef enum { TSQR_METHOD_CHOLQR = 1, TSQR_METHOD_INDIRECT = 2 } tsqr_method;
+tsqr_status tsqr_indirect_workspace_bytes(int32_t method, int32_t refine, int64_t m, int64_t n,
+                                          const tsqr_opts *opts, size_t *bytes);
+tsqr_status tsqr_qr_indirect(int32_t method, int32_t refine, int64_t m, int64_t n, const double *A,
+                             int64_t lda, double *Q, int64_t ldq, double *R, int64_t ldr, void *ws,
+                             size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
+                             void *stream);
 
 /* ------------------------------------------------------------------------------------------
  * Error metrics of Sec. I-B (measurement, not part of the factorization).  Compensated Gram

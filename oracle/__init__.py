@@ -62,6 +62,9 @@ def _load():
         lib.oracle_norm2.restype = dbl
         lib.oracle_residual_norm2.argtypes = [i64, i64, dp, i64, dp, i64, dp, i64, i32]
         lib.oracle_residual_norm2.restype = dbl
+        lib.oracle_indirect_qr.argtypes = [i32, i32, i64, i64, dp, i64, i64, dp, i64, dp, i64,
+                                           i32]
+        lib.oracle_indirect_qr.restype = i32
         lib.oracle_max_threads.argtypes = [i32]
         lib.oracle_max_threads.restype = i32
         _lib = lib
@@ -209,3 +212,25 @@ def metric_svd_backward(A, U, S, V, normA=None, nthreads: int = 0) -> float:
         normA = norm2(A, nthreads)
     B = np.asarray(S)[:, None] * np.asarray(V).T
     return residual(A, U, B, nthreads) / normA
+
+
+METHODS = {"cholqr": (1, 0), "cholqr_ir": (1, 1), "indirect": (2, 0), "indirect_ir": (2, 1)}
+
+
+def indirect_qr(A, method: str, block_rows: int = 1000, nthreads: int = 0):
+    """The comparison methods of the stability experiment (Sec. IV): Cholesky QR (Sec. II-A) or
+    indirect TSQR (Sec. II-B) with Q = A R^{-1} (Sec. II-C), and the "_ir" variants with one step
+    of iterative refinement.  Returns (Q, R), or None when the Cholesky factorization breaks
+    down."""
+    A = _c(A)
+    m, n = A.shape
+    meth, ir = METHODS[method]
+    Q = np.empty((m, n))
+    R = np.empty((n, n))
+    st = _load().oracle_indirect_qr(meth, ir, m, n, _p(A), n, block_rows, _p(Q), n, _p(R), n,
+                                    nthreads)
+    if st == 4:
+        return None
+    if st != 0:
+        raise ValueError("oracle_indirect_qr failed with status %d" % st)
+    return Q, R

@@ -18,6 +18,12 @@
  *   Sec. III-B      direct TSQR: step 1 local QR per row block, step 2 QR of the stacked R_i
  *                   (the k-th n-row block of that Q is the block for the k-th map task), step 3
  *                   Q_i = Q1_i * Q2_i;  SVD variant: SVD of R, then U = Q U_R.
+ *   Sec. II-A       Cholesky QR: A^T A summed from the row blocks' A_p^T A_p (Alg. 1), R^T = its
+ *                   Cholesky factor.
+ *   Sec. II-B/II-C  indirect TSQR: R from the stacked-R reduction alone, Q = A R^{-1} by the
+ *                   explicit inverse of R; iterative refinement = the same QR repeated once on the
+ *                   computed Q (Sec. I).  These are the comparison methods of the stability
+ *                   experiment of Sec. IV.
  * The adjoints (qr/svd backward) are not in the paper; they follow the published closed forms
  * named at each function.
  */
@@ -613,4 +619,133 @@ double oracle_residual_norm2(int64_t m, int64_t n, const double *A, int64_t lda,
     double res = oracle_norm2(m, n, E, n, nthreads);
     free(E);
     return res;
+}
+
+
+/* ---------------------------------------------------------------------------------------------
+ * Comparison methods of the stability experiment (Sec. IV): Cholesky QR (Sec. II-A) and indirect
+ * TSQR (Sec. II-B), each with Q = A R^{-1} (Sec. II-C) and optionally one step of iterative
+ * refinement (the same QR repeated on the computed Q, Sec. I): Q1 R1 = A, Q R2 = Q1, R = R2 R1.
+ * ------------------------------------------------------------------------------------------- */
+#define ORACLE_CHOLQR 1
+#define ORACLE_INDIRECT 2
+#define ERR_BREAKDOWN 4
+
+/* R^{-1} of an upper-triangular n x n R (ld n), column by column: R x = e_j by back substitution. */
+static void upper_inverse(int64_t n, const double *R, double *X)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        for (int64_t i = n - 1; i >= 0; --i) {
+            double acc = (i == j) ? 1.0 : 0.0;
+            for (int64_t t = i + 1; t < n; ++t) acc -= R[i * n + t] * X[t * n + j];
+            X[i * n + j] = (i <= j) ? acc / R[i * n + i] : 0.0;
+        }
+    }
+}
+
+/* Q = A X for an m x n A and an n x n X (plain triple loop, rows in parallel). */
+static void times_small(int64_t m, int64_t n, const double *A, int64_t lda, const double *X,
+                        double *Q, int64_t ldq)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < m; ++i)
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < n; ++k) acc += A[i * lda + k] * X[k * n + j];
+            Q[i * ldq + j] = acc;
+        }
+}
+
+/* One QR of A by `method`: R (n x n, ld n) and Q = A R^{-1} (ld ldq).  Cholesky QR: the Gram
+ * matrix is summed block by block as the map tasks of Alg. 1 produce it (blocks of block_rows
+ * rows, each A_p^T A_p accumulated over its rows, then the blocks added in order); G = L L^T by
+ * the column-by-column Cholesky algorithm, R = L^T.  Returns ERR_BREAKDOWN when a pivot is not
+ * positive (G not numerically positive definite). */
+static int one_qr(int method, int64_t m, int64_t n, const double *A, int64_t lda,
+                  int64_t block_rows, double *Q, int64_t ldq, double *R)
+{
+    if (method == ORACLE_INDIRECT) {
+        int st = oracle_tsqr(m, n, A, lda, block_rows, NULL, 0, R, n, NULL, 0);
+        if (st != OK) return st;
+    } else {
+        double *G = calloc((size_t)(n * n), sizeof(double));
+        double *Gp = malloc(sizeof(double) * (size_t)(n * n));
+        if (!G || !Gp) { free(G); free(Gp); return ERR_NOMEM; }
+        for (int64_t r0 = 0; r0 < m; r0 += block_rows) {
+            int64_t r1 = (r0 + block_rows < m) ? r0 + block_rows : m;
+            for (int64_t e = 0; e < n * n; ++e) Gp[e] = 0.0;
+            for (int64_t i = r0; i < r1; ++i)
+                for (int64_t a = 0; a < n; ++a)
+                    for (int64_t b = 0; b < n; ++b) Gp[a * n + b] += A[i * lda + a] * A[i * lda + b];
+            for (int64_t e = 0; e < n * n; ++e) G[e] += Gp[e];
+        }
+        free(Gp);
+        /* G = L L^T; L stored transposed into R (R = L^T) */
+        for (int64_t e = 0; e < n * n; ++e) R[e] = 0.0;
+        int bad = 0;
+        for (int64_t j = 0; j < n && !bad; ++j) {
+            double d = G[j * n + j];
+            for (int64_t k = 0; k < j; ++k) d -= R[k * n + j] * R[k * n + j];
+            if (!(d > 0.0)) { bad = 1; break; }
+            double ljj = sqrt(d);
+            R[j * n + j] = ljj;
+            for (int64_t i = j + 1; i < n; ++i) {
+                double x = G[i * n + j];
+                for (int64_t k = 0; k < j; ++k) x -= R[k * n + i] * R[k * n + j];
+                R[j * n + i] = x / ljj;
+            }
+        }
+        free(G);
+        if (bad) return ERR_BREAKDOWN;
+    }
+    double *X = malloc(sizeof(double) * (size_t)(n * n));
+    if (!X) return ERR_NOMEM;
+    upper_inverse(n, R, X);
+    times_small(m, n, A, lda, X, Q, ldq);
+    free(X);
+    return OK;
+}
+
+/*
+ * Cholesky QR (method 1) or indirect TSQR (method 2), with `refine` steps of iterative refinement
+ * (0 or 1).  Q: m x n (ldq), R: n x n (ldr).  Returns 0, or ERR_BREAKDOWN (Cholesky of a Gram
+ * matrix that is not numerically positive definite; Q and R are then not written).
+ */
+int oracle_indirect_qr(int method, int refine, int64_t m, int64_t n, const double *A, int64_t lda,
+                       int64_t block_rows, double *Q, int64_t ldq, double *R, int64_t ldr,
+                       int nthreads)
+{
+    if (m <= 0 || n <= 0 || !A || !Q || !R || lda < n || ldq < n || ldr < n) return ERR_ARG;
+    if (method != ORACLE_CHOLQR && method != ORACLE_INDIRECT) return ERR_ARG;
+    if (m < n) return ERR_SHAPE;
+    set_threads(nthreads);
+    double *R1 = malloc(sizeof(double) * (size_t)(n * n));
+    double *Q1 = refine ? malloc(sizeof(double) * (size_t)(m * n)) : NULL;
+    if (!R1 || (refine && !Q1)) { free(R1); free(Q1); return ERR_NOMEM; }
+    int st = one_qr(method, m, n, A, lda, block_rows, refine ? Q1 : Q, refine ? n : ldq, R1);
+    if (st == OK && refine) {
+        double *R2 = malloc(sizeof(double) * (size_t)(n * n));
+        if (!R2) st = ERR_NOMEM;
+        else {
+            st = one_qr(method, m, n, Q1, n, block_rows, Q, ldq, R2);
+            if (st == OK) { /* R = R2 R1 */
+                double *T = malloc(sizeof(double) * (size_t)(n * n));
+                for (int64_t i = 0; i < n; ++i)
+                    for (int64_t j = 0; j < n; ++j) {
+                        double acc = 0.0;
+                        for (int64_t k = 0; k < n; ++k) acc += R2[i * n + k] * R1[k * n + j];
+                        T[i * n + j] = acc;
+                    }
+                memcpy(R1, T, sizeof(double) * (size_t)(n * n));
+                free(T);
+            }
+            free(R2);
+        }
+    }
+    if (st == OK)
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t j = 0; j < n; ++j) R[i * ldr + j] = R1[i * n + j];
+    free(R1);
+    free(Q1);
+    return st;
 }

@@ -54,6 +54,9 @@ SIGNATURES = {
     "tsqr_profile_collect": (_i32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64), _i32]),
     "tsqr_profile_num_classes": (_i32, []),
     "tsqr_profile_class_name": (ctypes.c_char_p, [_i32]),
+    "tsqr_indirect_workspace_bytes": (_i32, [_i32, _i32, _i64, _i64, _vp, ctypes.POINTER(_sz)]),
+    "tsqr_qr_indirect": (_i32, [_i32, _i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz,
+                                _vp, _vp, _vp]),
     "tsqr_metric_workspace_bytes": (_i32, [_i64, _i64, ctypes.POINTER(_sz)]),
     "tsqr_metric_gram": (_i32, [_i32, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _sz,
                                 _vp]),

@@ -358,6 +358,66 @@ tsqr_status do_svd(int in_dtype, int64_t m, int64_t n, const void *A, int64_t ld
     return run_apply_levels(pl, ws, in_dtype, U, ldu, (int)n, nullptr, 0, st);
 }
 
+// Comparison methods of the stability experiment (Sec. IV): workspace = the R-only plan of
+// indirect TSQR, then R1, Rinv, R2 (n x n), the Gram G and its row-block partials, and Q1 (m x n)
+// when refining.
+struct IndirLayout {
+    Plan pr;
+    size_t r1 = 0, rinv = 0, r2 = 0, g = 0, part = 0, q1 = 0, total = 0;
+};
+
+tsqr_status build_indirect_layout(int method, int refine, int64_t m, int64_t n, const tsqr_opts *o,
+                                  IndirLayout &L)
+{
+    if (method != TSQR_METHOD_CHOLQR && method != TSQR_METHOD_INDIRECT) return TSQR_ERR_INVALID_ARG;
+    if (refine != 0 && refine != 1) return TSQR_ERR_INVALID_ARG;
+    if (o && o->precision != TSQR_FP64) return TSQR_ERR_UNSUPPORTED;
+    tsqr_status s = build_plan(OP_R, m, n, F64, o, false, false, L.pr);
+    if (s != TSQR_OK) return s;
+    size_t off = align_up(L.pr.total);
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return at;
+    };
+    const size_t nn = sizeof(double) * (size_t)n * n;
+    L.r1 = take(nn);
+    L.rinv = take(nn);
+    L.r2 = take(nn);
+    L.g = take(nn);
+    L.part = take(nn * (size_t)gram_blocks(m));
+    if (refine) L.q1 = take(sizeof(double) * (size_t)m * n);
+    L.total = off;
+    return TSQR_OK;
+}
+
+// One QR by `method` of X (m x n, ldx): R (n x n, ld n) and Qout = X R^{-1} (ldq).
+tsqr_status one_indirect_qr(int method, const IndirLayout &L, int64_t m, int64_t n, const double *X,
+                            int64_t ldx, double *Qout, int64_t ldq, double *R, void *ws,
+                            int32_t *d_info, int keep_info, hipStream_t st)
+{
+    double *Rinv = (double *)wsp(ws, L.rinv);
+    if (method == TSQR_METHOD_CHOLQR) {
+        ProfScope ps(PC_BWD_GRAM, st);
+        TSQR_HIP_CHECK(launch_gram(m, n, X, ldx, X, ldx, (double *)wsp(ws, L.part),
+                                   (double *)wsp(ws, L.g), st));
+        TSQR_HIP_CHECK(launch_cholqr_small(n, (const double *)wsp(ws, L.g), R, Rinv, d_info,
+                                           keep_info, st));
+    } else {
+        tsqr_status s = run_factor_levels(L.pr, X, ldx, ws, st);
+        if (s != TSQR_OK) return s;
+        ProfScope ps(PC_FINALIZE, st);
+        TSQR_HIP_CHECK(launch_finalize(n, (const double *)wsp(ws, L.pr.lev[L.pr.nlev - 1].s), R,
+                                       nullptr, n, nullptr, 0, 0, 0, nullptr, nullptr, nullptr,
+                                       nullptr, 0, nullptr, nullptr, d_info, st, keep_info));
+        TSQR_HIP_CHECK(launch_rinv_small(n, R, Rinv, st));
+    }
+    ProfScope ps(PC_BWD_GEMM, st);
+    TSQR_HIP_CHECK(launch_gemm_mfma(F64, F64, m, n, 256, X, ldx, Rinv, n, 0, (int)n, Qout, ldq,
+                                    (int)n, nullptr, 0, 0, st));
+    return TSQR_OK;
+}
+
 // Backward workspace: the forward plan's workspace, then the recomputed factor and the adjoint
 // scratch.
 struct BwdLayout {
@@ -555,6 +615,47 @@ tsqr_status tsqr_svd_f32(int64_t m, int64_t n, const float *A, int64_t lda, floa
 {
     return do_svd(F32, m, n, A, lda, U, ldu, S, V, ldv, Q, ldq, R, ldr, ws, ws_bytes, d_info, opts,
                   stream);
+}
+
+tsqr_status tsqr_indirect_workspace_bytes(int32_t method, int32_t refine, int64_t m, int64_t n,
+                                          const tsqr_opts *opts, size_t *bytes)
+{
+    if (!bytes) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    IndirLayout L;
+    tsqr_status s = build_indirect_layout(method, refine, m, n, opts_or_default(opts, tmp), L);
+    if (s != TSQR_OK) return s;
+    *bytes = L.total;
+    return TSQR_OK;
+}
+
+tsqr_status tsqr_qr_indirect(int32_t method, int32_t refine, int64_t m, int64_t n, const double *A,
+                             int64_t lda, double *Q, int64_t ldq, double *R, int64_t ldr, void *ws,
+                             size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts, void *stream)
+{
+    if (!A || !Q || !R || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldq < n || ldr < n) return TSQR_ERR_INVALID_ARG;
+    tsqr_opts tmp;
+    IndirLayout L;
+    tsqr_status s = build_indirect_layout(method, refine, m, n, opts_or_default(opts, tmp), L);
+    if (s != TSQR_OK) return s;
+    if (!ws || ws_bytes < L.total) return TSQR_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    double *R1 = (double *)wsp(ws, L.r1), *R2 = (double *)wsp(ws, L.r2);
+    if (!refine) {
+        if ((s = one_indirect_qr(method, L, m, n, A, lda, Q, ldq, R1, ws, d_info, 0, st)) != TSQR_OK)
+            return s;
+        TSQR_HIP_CHECK(launch_trmul_small(n, nullptr, R1, R, ldr, st));
+        return TSQR_OK;
+    }
+    // iterative refinement (Sec. I): Q1 R1 = A, Q R2 = Q1, R = R2 R1
+    double *Q1 = (double *)wsp(ws, L.q1);
+    if ((s = one_indirect_qr(method, L, m, n, A, lda, Q1, n, R1, ws, d_info, 0, st)) != TSQR_OK)
+        return s;
+    if ((s = one_indirect_qr(method, L, m, n, Q1, n, Q, ldq, R2, ws, d_info, 1, st)) != TSQR_OK)
+        return s;
+    TSQR_HIP_CHECK(launch_trmul_small(n, R2, R1, R, ldr, st));
+    return TSQR_OK;
 }
 
 tsqr_status tsqr_plan_levels(int32_t op, int64_t m, int64_t n, const tsqr_opts *opts,

@@ -148,4 +148,13 @@ hipError_t launch_refine(int64_t m, int64_t n, const double *A, int64_t lda, con
                          double *Q, int64_t ldq, double *R, int64_t ldr, void *scratch,
                          int32_t *info, hipStream_t st);
 
+// ---- launchers (indirect.hip): comparison methods of the stability experiment --------------
+// Cholesky of the Gram G (n x n): R = L^T and Rinv = R^{-1} (info = -4 on breakdown).
+hipError_t launch_cholqr_small(int64_t n, const double *G, double *R, double *Rinv, int32_t *info,
+                               int keep_info, hipStream_t st);
+hipError_t launch_rinv_small(int64_t n, const double *R, double *Rinv, hipStream_t st);
+// Rout (ldr) = R2 R1 for upper-triangular n x n factors (ld n).
+hipError_t launch_trmul_small(int64_t n, const double *R2, const double *R1, double *Rout,
+                              int64_t ldr, hipStream_t st);
+
 }  // namespace tsqr

@@ -373,3 +373,32 @@ def metric_norm2(A: torch.Tensor) -> float:
 def metric_residual(A: torch.Tensor, Q: torch.Tensor, B: torch.Tensor) -> float:
     """||A - Q B||_2 with compensated residual rows."""
     return _sym_norm2(metric_gram(1, Q, A, B)) ** 0.5
+
+
+# ----------------------------------------------------------------------------- comparison methods
+_METHODS = {"cholqr": (1, 0), "cholqr_ir": (1, 1), "indirect": (2, 0), "indirect_ir": (2, 1)}
+
+
+def qr_indirect(A: torch.Tensor, method: str, out=None, ws: torch.Tensor | None = None,
+                info: torch.Tensor | None = None):
+    """The stability experiment's comparison methods (Sec. IV) on the GPU: "cholqr" (Sec. II-A),
+    "indirect" (Sec. II-B), each with Q = A R^{-1} (Sec. II-C), and their "_ir" variants with one
+    step of iterative refinement.  Returns (Q, R, info) with info the device status (-4: the
+    Cholesky factorization broke down)."""
+    _require_gpu_matrix(A)
+    m, n = A.shape
+    meth, ir = _METHODS[method]
+    Q, R = out if out is not None else (torch.empty((m, n), dtype=A.dtype, device=A.device),
+                                        torch.empty((n, n), dtype=A.dtype, device=A.device))
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    o = make_opts("fp64", 0)
+    if ws is None:
+        nb = ctypes.c_size_t(0)
+        check(lib().tsqr_indirect_workspace_bytes(meth, ir, m, n, ctypes.byref(o), ctypes.byref(nb)),
+              "tsqr_indirect_workspace_bytes")
+        ws = torch.empty(int(nb.value), dtype=torch.uint8, device=A.device)
+    check(lib().tsqr_qr_indirect(meth, ir, m, n, _p(A), A.stride(0), _p(Q), Q.stride(0), _p(R),
+                                 R.stride(0), _p(ws), ws.numel(), _p(info), ctypes.byref(o),
+                                 _stream(A.device)), "tsqr_qr_indirect")
+    return Q, R, info

@@ -183,15 +183,20 @@ def test_partition_merges_short_tail():
 
 
 def test_q2_block_layout():
-    """Sec. III-B: the k-th n-row block of the step-2 Q pairs with the k-th row block."""
+    """Sec. III-B: the k-th n-row block of the step-2 Q pairs with the k-th row block: stacking
+    the local factors gives [R_1; ...; R_P] = Q2 R, so Q2_k R is block k's own R factor, which
+    LAPACK computes independently up to the signs of its rows."""
     A = np.random.default_rng(14).standard_normal((120, 4))
     Q, R, Q2 = oracle.tsqr(A, block_rows=30, want_q2=True)
-    for k in range(4):
-        Qk, Rk = np.linalg.qr(A[30 * k:30 * (k + 1)])
-        # Q_k R_k Q2_k^... : block k of A equals Q1_k R_k = Q_k-rows R; check A_k = Q[k] R
-        assert np.abs(A[30 * k:30 * (k + 1)] - Q[30 * k:30 * (k + 1)] @ R).max() <= 1e-13
-    assert np.abs(Q2.T @ Q2 - np.eye(4)).max() <= 1e-14
     assert Q2.shape == (16, 4)
+    assert np.abs(Q2.T @ Q2 - np.eye(4)).max() <= 1e-14
+    for k in range(4):
+        Rk = np.linalg.qr(A[30 * k:30 * (k + 1)], mode="r")
+        got = Q2[4 * k:4 * (k + 1)] @ R
+        d = np.sign(np.diag(got)) * np.sign(np.diag(Rk))      # row signs are free
+        assert np.abs(got - d[:, None] * Rk).max() <= 1e-13 * np.abs(Rk).max()
+        # and block k of A is reproduced by its rows of Q
+        assert np.abs(A[30 * k:30 * (k + 1)] - Q[30 * k:30 * (k + 1)] @ R).max() <= 1e-13
 
 
 # ----------------------------------------------------------------------------- SVD
@@ -316,3 +321,75 @@ def test_metrics_report_nan_for_nonfinite_input():
     assert np.isnan(oracle.metric_orth(Q))
     A = np.random.default_rng(23).standard_normal((100, 3))
     assert np.isnan(oracle.metric_backward(A, Q, np.eye(3)))
+
+
+
+# ----------------------------------------------------------------------------- comparison methods
+def test_cholesky_qr_library_special_case():
+    """Sec. II-A: R^T is the Cholesky factor of A^T A, and Q = A R^{-1} (Sec. II-C)."""
+    A = np.random.default_rng(41).standard_normal((500, 6))
+    Q, R = oracle.indirect_qr(A, "cholqr", block_rows=64)
+    L = np.linalg.cholesky(A.T @ A)
+    assert rel(R, L.T) <= 1e-13
+    assert np.abs(Q - A @ np.linalg.inv(L.T)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("m,n,seed", [(20, 4, 42), (48, 6, 43)])
+def test_cholesky_qr_matches_exact_gram(m, n, seed):
+    A = np.random.default_rng(seed).standard_normal((m, n))
+    Q, R = oracle.indirect_qr(A, "cholqr", block_rows=7)
+    assert rel(R, chol_exact_gram(A)) <= 1e-13
+
+
+def test_indirect_q_is_a_times_the_inverse():
+    """Sec. II-B / II-C: the indirect method's R is the TSQR R, its Q is A times R^{-1}."""
+    A = np.random.default_rng(44).standard_normal((400, 5))
+    Q, R = oracle.indirect_qr(A, "indirect", block_rows=50)
+    Rt = oracle.tsqr(A, block_rows=50, want_q=False)
+    assert np.array_equal(R, Rt)
+    assert np.abs(Q - A @ np.linalg.inv(R)).max() <= 1e-13
+
+
+@pytest.mark.parametrize("method", ["cholqr", "indirect"])
+def test_refinement_is_the_qr_repeated_on_q(method):
+    """Sec. I: iterative refinement repeats the QR on the computed Q: Q1 R1 = A, Q R2 = Q1,
+    R = R2 R1."""
+    A = workloads.spectrum_matrix(3000, 6, 5.0, seed=45)[0]
+    Q, R = oracle.indirect_qr(A, method + "_ir", block_rows=500)
+    Q1, R1 = oracle.indirect_qr(A, method, block_rows=500)
+    Q2, R2 = oracle.indirect_qr(Q1, method, block_rows=500)
+    assert np.array_equal(Q, Q2)
+    assert rel(R, R2 @ R1) <= 1e-15
+
+
+@pytest.mark.parametrize("log_cond", list(range(0, 17)))
+def test_stability_experiment_claims(log_cond):
+    """Sec. IV on 20,000 x 10 matrices with s = logspace(0, -c, 10): direct TSQR stays at ~1e-15
+    orthogonality; Q = A R^{-1} loses orthogonality in proportion to kappa (indirect TSQR) or
+    kappa^2 (Cholesky QR); Cholesky QR fails from kappa = 1e8 on; one step of iterative
+    refinement brings the indirect methods back to ~1e-15 where their first Q is still of full
+    numerical rank; every method that completes has an O(eps) backward error (Sec. I-B)."""
+    c = log_cond
+    A = workloads.spectrum_matrix(20_000, 10, float(c), seed=500 + c)[0]
+    normA = oracle.norm2(A)
+    kappa = 10.0 ** c
+    u = EPS / 2
+    Qd, Rd = oracle.tsqr(A, block_rows=1000)
+    assert oracle.metric_orth(Qd) <= 1e-14
+    res = {m: oracle.indirect_qr(A, m) for m in ("cholqr", "cholqr_ir", "indirect", "indirect_ir")}
+    orth = {m: (oracle.metric_orth(r[0]) if r is not None else np.inf) for m, r in res.items()}
+    for m, r in res.items():
+        if r is not None:
+            assert oracle.metric_backward(A, r[0], r[1], normA) <= 1e-14, m
+    if 4 <= c <= 13:
+        assert 1e-2 * u * kappa <= orth["indirect"] <= 1e2 * u * kappa
+    if c <= 2:
+        assert orth["cholqr"] <= 1e-12
+    elif c <= 6:
+        assert 1e-3 * u * kappa ** 2 <= orth["cholqr"] <= 1e3 * u * kappa ** 2
+    elif c >= 8:
+        assert orth["cholqr"] >= 0.1          # fails: breakdown (inf) or no orthogonality left
+    if c <= 7:
+        assert orth["cholqr_ir"] <= 1e-14
+    if c <= 15:
+        assert orth["indirect_ir"] <= 1e-14
