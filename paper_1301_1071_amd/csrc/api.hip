@@ -152,6 +152,8 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         lv.panels = ceil_div(rows, lv.b);
         const size_t es = elem_size(lv.dtype);
         if (need_q) lv.q1 = take(es * (size_t)rows * n);
+        // register panels with n <= 64 keep V and K (Q1 = [I; 0] - V K) instead of forming Q1
+        if (need_q && lv.reg && n <= 64) lv.kv = take(es * (size_t)lv.panels * n * n);
         lv.s = take(sizeof(double) * (size_t)lv.panels * n * n);
         if (need_q && L >= 1) lv.x = take(sizeof(double) * (size_t)rows * pl.k);
         if (lv.global) lv.gpanel = take(es * (size_t)lv.panels * n * (lv.b + 1));
@@ -189,7 +191,8 @@ tsqr_status run_factor_levels(const Plan &pl, const void *A, int64_t lda, void *
         ProfScope ps(L == 0 ? PC_FACTOR0 : PC_FACTOR_TREE, st);
         if (lv.reg)
             TSQR_HIP_CHECK(launch_factor_reg(in_dt, lv.dtype, lv.rows, pl.n, X, ldx,
-                                             wsp(ws, lv.q1), (double *)wsp(ws, lv.s), st));
+                                             wsp(ws, lv.q1), (double *)wsp(ws, lv.s),
+                                             wsp(ws, lv.kv), st));
         else
             TSQR_HIP_CHECK(launch_factor(in_dt, lv.dtype, lv.rows, pl.n, lv.b, X, ldx,
                                          wsp(ws, lv.q1), (double *)wsp(ws, lv.s),
@@ -210,14 +213,15 @@ tsqr_status run_apply_levels(const Plan &pl, void *ws, int out_dtype, void *out0
         if (L > 0) {
             double *X = (double *)wsp(ws, lv.x);
             TSQR_HIP_CHECK(launch_apply_mfma(F64, F64, lv.rows, pl.n, lv.b, wsp(ws, lv.q1), W,
-                                             ldw, wstride, pl.k, X, pl.k, pl.k, nullptr, 0, st));
+                                             ldw, wstride, pl.k, X, pl.k, pl.k, nullptr, 0,
+                                             wsp(ws, lv.kv), st));
             W = X;
             ldw = pl.k;
             wstride = pl.n;
         } else {
             TSQR_HIP_CHECK(launch_apply_mfma(lv.dtype, out_dtype, lv.rows, pl.n, lv.b,
                                              wsp(ws, lv.q1), W, ldw, wstride, pl.k, out0, ld0,
-                                             k0, out1, ld1, st));
+                                             k0, out1, ld1, wsp(ws, lv.kv), st));
         }
     }
     return TSQR_OK;

@@ -17,7 +17,7 @@ __global__ void __launch_bounds__(kWaves * 64)
 k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, int64_t ldq,
              const double *__restrict__ W, int64_t ldw, int64_t wstride, int k,
              To *__restrict__ out0, int64_t ld0, int k0, To *__restrict__ out1, int64_t ld1,
-             int accumulate, int64_t panels, int ny, int nrc)
+             int accumulate, int64_t panels, int ny, int nrc, const T *__restrict__ kmat)
 {
     const int64_t bid = blockIdx.x;
     const int S = ny * nrc;
@@ -28,13 +28,14 @@ k_apply_mfma(int64_t rows, int n, int b, const T *__restrict__ q1, int64_t ldq,
     const int64_t p = grp * 8 + (rem & 7);
     if (p >= panels) return;
     apply_mfma_panel<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1,
-                                ld1, accumulate, p, y * 16 * NT, rc, nrc);
+                                ld1, accumulate, p, y * 16 * NT, rc, nrc, kmat);
 }
 
 template <typename T, typename To, int NT>
 hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t ldq,
                          const double *W, int64_t ldw, int64_t wstride, int k, void *out0,
-                         int64_t ld0, int k0, void *out1, int64_t ld1, int acc, hipStream_t st)
+                         int64_t ld0, int k0, void *out1, int64_t ld1, int acc, const void *kmat,
+                         hipStream_t st)
 {
     const size_t lds = apply_lds_bytes<T, NT>(n);
     auto kern = k_apply_mfma<T, To, NT>;
@@ -50,14 +51,15 @@ hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t
     const int64_t blocks = ceil_div(panels, 8) * 8 * ny * nrc;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kWaves * 64), lds, st, rows, (int)n, b,
                        (const T *)q1, ldq, W, ldw, wstride, k, (To *)out0, ld0, k0, (To *)out1,
-                       ld1, acc, panels, ny, nrc);
+                       ld1, acc, panels, ny, nrc, (const T *)kmat);
     return hipGetLastError();
 }
 
 template <typename T, typename To>
 hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t ldq,
                         const double *W, int64_t ldw, int64_t wstride, int k, void *out0,
-                        int64_t ld0, int k0, void *out1, int64_t ld1, int acc, hipStream_t st)
+                        int64_t ld0, int k0, void *out1, int64_t ld1, int acc, const void *kmat,
+                        hipStream_t st)
 {
     // Column slices per panel: as few as keep a work-group within 8 output tiles and 80 KB of
     // LDS (the W image plus the staged Q1 blocks), so that two work-groups share a CU.  Every
@@ -70,7 +72,7 @@ hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t 
 #define TSQR_NT(NT)                                                                           \
     case NT:                                                                                  \
         return apply_mfma_nt<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, \
-                                        out1, ld1, acc, st)
+                                        out1, ld1, acc, kmat, st)
     switch (nt_of(ny)) {
         TSQR_NT(1);
         TSQR_NT(2);
@@ -87,33 +89,44 @@ hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t 
 
 }  // namespace
 
+hipError_t launch_apply_vk(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
+                          const void *q1, int64_t ldq, const double *W, int64_t ldw,
+                          int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
+                          int64_t ld1, int accumulate, const void *kmat, hipStream_t st)
+{
+    if (n > 4 * kMaxKC) return hipErrorInvalidValue;
+    if (kmat && (n > 64 || accumulate)) return hipErrorInvalidValue;
+    if (q_dtype == F64) {
+        if (out_dtype == F64)
+            return apply_mfma_t<double, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0,
+                                                k0, out1, ld1, accumulate, kmat, st);
+        return apply_mfma_t<double, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
+                                           out1, ld1, accumulate, kmat, st);
+    }
+    if (out_dtype == F64)
+        return apply_mfma_t<float, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
+                                           out1, ld1, accumulate, kmat, st);
+    return apply_mfma_t<float, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1,
+                                      ld1, accumulate, kmat, st);
+}
+
 hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                             const void *q1, int64_t ldq, const double *W, int64_t ldw,
                             int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
                             int64_t ld1, int accumulate, hipStream_t st)
 {
     if (n > 4 * kMaxKC) return hipErrorInvalidValue;
-    if (q_dtype == F64) {
-        if (out_dtype == F64)
-            return apply_mfma_t<double, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0,
-                                                k0, out1, ld1, accumulate, st);
-        return apply_mfma_t<double, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
-                                           out1, ld1, accumulate, st);
-    }
-    if (out_dtype == F64)
-        return apply_mfma_t<float, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
-                                           out1, ld1, accumulate, st);
-    return apply_mfma_t<float, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1,
-                                      ld1, accumulate, st);
+    return launch_apply_vk(q_dtype, out_dtype, rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0,
+                           k0, out1, ld1, accumulate, nullptr, st);
 }
 
 hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                              const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
                              void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
-                             hipStream_t st)
+                             const void *kmat, hipStream_t st)
 {
-    return launch_gemm_mfma(q_dtype, out_dtype, rows, n, b, q1, n, W, ldw, wstride, k, out0, ld0,
-                            k0, out1, ld1, 0, st);
+    return launch_apply_vk(q_dtype, out_dtype, rows, n, b, q1, n, W, ldw, wstride, k, out0, ld0, k0,
+                           out1, ld1, 0, kmat, st);
 }
 
 }  // namespace tsqr

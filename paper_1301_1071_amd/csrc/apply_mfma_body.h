@@ -40,14 +40,17 @@ constexpr int kMaxKC = 32;      // n <= 128
 constexpr int kWaves = 4;
 
 // One panel.  ACC: add to the output instead of overwriting it; WIDE: n > 64 (lane l also holds
-// column l + 64 of a row).
-template <typename T, typename To, int NT, bool ACC, bool WIDE>
+// column l + 64 of a row).  VK: q1 holds the panel's reflectors V and kmat its n x n K
+// (Q1 = [I; 0] - V K), and the product is Q1 W = [W; 0] - V (K W): the staged operand is -K W
+// instead of W, and W is added to the panel's top n rows.
+template <typename T, typename To, int NT, bool ACC, bool WIDE, bool VK>
 __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
                                                  const T *__restrict__ q1, int64_t ldq,
                                                  const double *__restrict__ W, int64_t ldw,
                                                  int64_t wstride, int k, To *__restrict__ out0,
                                                  int64_t ld0, int k0, To *__restrict__ out1,
-                                                 int64_t ld1, int64_t p, int j0, int rc, int nrc)
+                                                 int64_t ld1, int64_t p, int j0, int rc, int nrc,
+                                                 const T *__restrict__ kmat)
 {
     typedef typename Mfma<T>::acc_t acc_t;
     extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -82,6 +85,25 @@ __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
             if constexpr (WIDE) pre2[r] = row[c1];
         }
     };
+    if constexpr (VK) {
+        // K_p (row-major, ld n) is staged into this work-group's A-block area and W into wl as
+        // usual (below); after a barrier the waves form the tiles (a, t) of M = K W on the matrix
+        // cores from LDS (K upper triangular: K-chunks q >= 4 a only), hold them in registers
+        // across a second barrier, and overwrite wl with -M in the same B-operand order.
+        static_assert(!WIDE, "the V + K form is for n <= 64");
+        const T *Kp = kmat + p * (int64_t)n * n;
+        T *ks = as_all;                                   // n x n, ld n (fits the A-block area)
+        // all of a thread's loads first (n <= 64: at most 16 per thread), then the stores, so
+        // the loads are in flight together instead of one memory round trip each
+        constexpr int KPT = 64 * 64 / (kWaves * 64);
+        T kv[KPT];
+        const int nn = n * n;
+#pragma unroll
+        for (int u = 0; u < KPT; ++u) kv[u] = Kp[min(tid + u * kWaves * 64, nn - 1)];
+#pragma unroll
+        for (int u = 0; u < KPT; ++u)
+            if (tid + u * kWaves * 64 < nn) ks[tid + u * kWaves * 64] = kv[u];
+    }
     // W's loads go out eight at a time, so staging it waits for a few memory round trips rather
     // than one per value; the first block's loads are issued right after, before the barrier
     {
@@ -106,6 +128,42 @@ __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
                 if (e < total) wl[e] = v[u];
             }
         }
+    }
+    if constexpr (VK) {
+        constexpr int MT = 4 * NT;                        // at most (64 / 16) x NT tiles
+        constexpr int TPW = (MT + kWaves - 1) / kWaves;
+        const T *ks = as_all;
+        const int KT = (n + 15) >> 4;
+        const int l16 = lane & 15, lhi = lane >> 4;
+        __syncthreads();
+        acc_t macc[TPW];
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            macc[u] = acc_t{0, 0, 0, 0};
+            const int tile = w + kWaves * u;
+            if (tile >= KT * NT) continue;
+            const int a = tile / NT, t = tile - a * NT;
+            const int ar = min(16 * a + l16, n - 1);
+            const bool arok = 16 * a + l16 < n;
+            for (int q = 4 * a; q < KC; ++q) {
+                const int kr = 4 * q + lhi;
+                const T av = (arok && kr < n) ? ks[ar * n + min(kr, n - 1)] : T(0);
+                macc[u] = Mfma<T>::run(av, wl[(q * NT + t) * 64 + lane], macc[u]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < TPW; ++u) {
+            const int tile = w + kWaves * u;
+            if (tile >= KT * NT) continue;
+            const int a = tile / NT, t = tile - a * NT;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int r = 16 * a + Mfma<T>::row(lane, i);
+                if (r < 4 * KC) wl[((r >> 2) * NT + t) * 64 + (r & 3) * 16 + l16] = -macc[u][i];
+            }
+        }
+        // rows of -M past 4 KC do not exist; rows in [n, 4 KC) hold zeros (K's rows past n)
     }
     // this work-group's share of the panel's 16-row blocks: chunk rc of nrc, blocks dealt to the
     // waves in turn
@@ -162,6 +220,17 @@ __device__ __forceinline__ void apply_panel_impl(int64_t rows, int n, int b,
             const int jt = j0 + 16 * t;                 // uniform first column of the tile
             if (jt >= k) break;
             const bool jok = jl + 16 * t < k;
+            if constexpr (VK) {
+                // the [W; 0] term on the panel's top n rows
+                if (r0 < n) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int rr = r0 + Mfma<T>::row(lane, i);
+                        if (jok && rr < n && Mfma<T>::row(lane, i) < cnt)
+                            acc[t][i] += (T)Wp[(int64_t)rr * ldw + jl + 16 * t];
+                    }
+                }
+            }
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 if (!(jok && Mfma<T>::row(lane, i) < cnt)) continue;
@@ -181,11 +250,18 @@ __device__ __forceinline__ void apply_mfma_panel(int64_t rows, int n, int b,
                                                  int64_t wstride, int k, To *__restrict__ out0,
                                                  int64_t ld0, int k0, To *__restrict__ out1,
                                                  int64_t ld1, int accumulate, int64_t p, int j0,
-                                                 int rc = 0, int nrc = 1)
+                                                 int rc = 0, int nrc = 1,
+                                                 const T *__restrict__ kmat = nullptr)
 {
 #define TSQR_APPLY(ACC, WIDE)                                                                   \
-    apply_panel_impl<T, To, NT, ACC, WIDE>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, \
-                                           k0, out1, ld1, p, j0, rc, nrc)
+    apply_panel_impl<T, To, NT, ACC, WIDE, false>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, \
+                                                  ld0, k0, out1, ld1, p, j0, rc, nrc, nullptr)
+    if (kmat != nullptr && n <= 64) {
+        apply_panel_impl<T, To, NT, false, false, true>(rows, n, b, q1, ldq, W, ldw, wstride, k,
+                                                        out0, ld0, k0, out1, ld1, p, j0, rc, nrc,
+                                                        kmat);
+        return;
+    }
     if (n > 64) {
         if (accumulate) TSQR_APPLY(true, true);
         else TSQR_APPLY(false, true);

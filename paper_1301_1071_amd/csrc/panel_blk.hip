@@ -30,13 +30,13 @@ using namespace blklaunch;
 
 template <typename Tin, typename T>
 hipError_t factor_blk_dispatch(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
-                               double *S, hipStream_t st)
+                               double *S, void *kout, hipStream_t st)
 {
     switch ((n + 15) / 16) {
-    case 1: return factor_blk_launch<Tin, T, 1>(rows, n, X, ldx, q1, S, st);
-    case 2: return factor_blk_launch<Tin, T, 2>(rows, n, X, ldx, q1, S, st);
-    case 3: return factor_blk_launch<Tin, T, 3>(rows, n, X, ldx, q1, S, st);
-    default: return factor_blk_launch<Tin, T, 4>(rows, n, X, ldx, q1, S, st);
+    case 1: return factor_blk_launch<Tin, T, 1>(rows, n, X, ldx, q1, S, st, kout);
+    case 2: return factor_blk_launch<Tin, T, 2>(rows, n, X, ldx, q1, S, st, kout);
+    case 3: return factor_blk_launch<Tin, T, 3>(rows, n, X, ldx, q1, S, st, kout);
+    default: return factor_blk_launch<Tin, T, 4>(rows, n, X, ldx, q1, S, st, kout);
     }
 }
 
@@ -50,15 +50,17 @@ int reg_panel_rows(int64_t n, int dtype)
 }
 
 hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, const void *X,
-                             int64_t ldx, void *q1, double *S, hipStream_t st)
+                             int64_t ldx, void *q1, double *S, void *kout, hipStream_t st)
 {
     if (n < 1 || n > 128) return hipErrorInvalidValue;
     if (dtype == F64 && in_dtype != F64) return hipErrorInvalidValue;
-    if (n > 64)
+    if (n > 64) {
+        if (kout) return hipErrorInvalidValue;     // V + K form only for n <= 64
         return factor_blk_wide((int)((n + 15) / 16), in_dtype, dtype, rows, n, X, ldx, q1, S, st);
-    if (dtype == F64) return factor_blk_dispatch<double, double>(rows, n, X, ldx, q1, S, st);
-    if (in_dtype == F64) return factor_blk_dispatch<double, float>(rows, n, X, ldx, q1, S, st);
-    return factor_blk_dispatch<float, float>(rows, n, X, ldx, q1, S, st);
+    }
+    if (dtype == F64) return factor_blk_dispatch<double, double>(rows, n, X, ldx, q1, S, kout, st);
+    if (in_dtype == F64) return factor_blk_dispatch<double, float>(rows, n, X, ldx, q1, S, kout, st);
+    return factor_blk_dispatch<float, float>(rows, n, X, ldx, q1, S, kout, st);
 }
 
 }  // namespace tsqr

@@ -15,8 +15,14 @@
 //     tiles receive A <- (I - V T^T V^T) A through two products on the matrix cores:
 //     W = V^T A (the accumulator layout of V is directly the A operand of V^T) and A -= V (T^T W)
 //     (V re-laid out through LDS as the A operand);
-//   * the explicit Q1 = H_1 ... H_n [I; 0] is formed in place afterwards, block by block from
-//     the last, with the same two products and T in place of T^T, so step 3 stays a plain GEMM.
+//   * then either (FORM_Q1) the explicit Q1 = H_1 ... H_n [I; 0] is formed in place, block by
+//     block from the last, with the same two products and T in place of T^T, so that step 3 is a
+//     plain GEMM; or (STORE_VK, n <= 64) the reflectors V are stored with the n x n matrix
+//     K = T_p V1^T, T_p the compact-WY factor of the whole panel and V1 the top n rows of V, so
+//     that Q1 = [I; 0] - V K and step 3 forms Q1 W = [W; 0] - V (K W) without Q1 ever existing.
+//     T_p is assembled from the blocks' T and the cross products V_l^T V_j of the blocks:
+//     T_p[i][j] = -(sum_{l=i..j-1} T_p[i][l] V_l^T V_j) T_jj (tiles of 16).  This costs far fewer
+//     matrix-core operations than forming Q1 (no product over the panel's rows per block).
 //
 // Householder convention (as in the other panel kernels): beta = -sign(alpha) sqrt(alpha^2 + s2),
 // tau = (beta - alpha)/beta, v = [1; x/(alpha - beta)], tau = 0 when the column below the
@@ -76,6 +82,20 @@ template <> struct BlkT<double> {
         r = fma(r, fma(-x, r, 1.0), r);
         return fma(r, fma(-x, r, 1.0), r);
     }
+    // square root of x > 0 inside the normal range (column norms are formed unscaled, as the
+    // contract requires): the hardware reciprocal square root y, then coupled Newton iterations
+    // for g = x y ~ sqrt(x) and h = y / 2, and two residual corrections g += (x - g^2) h.  Without
+    // the range scaling of the general routine.  (x = 0 gives a NaN the caller discards.)
+    static __device__ __forceinline__ double sqrt_pos(double x)
+    {
+        const double y = __builtin_amdgcn_rsq(x);
+        double g = x * y, h = 0.5 * y;
+        const double r = fma(-g, h, 0.5);
+        g = fma(g, r, g);
+        h = fma(h, r, h);
+        g = fma(fma(-g, g, x), h, g);
+        return fma(fma(-g, g, x), h, g);
+    }
 };
 template <> struct BlkT<float> {
     typedef f4_t acc_t;
@@ -105,6 +125,15 @@ template <> struct BlkT<float> {
         float r = __builtin_amdgcn_rcpf(x);
         return fmaf(r, fmaf(-x, r, 1.0f), r);
     }
+    static __device__ __forceinline__ float sqrt_pos(float x)
+    {
+        const float y = __builtin_amdgcn_rsqf(x);
+        float g = x * y, h = 0.5f * y;
+        const float r = fmaf(-g, h, 0.5f);
+        g = fmaf(g, r, g);
+        h = fmaf(h, r, h);
+        return fmaf(fmaf(-g, g, x), h, g);
+    }
 };
 
 template <int I, int N, typename F> __device__ __forceinline__ void static_for(F &&f)
@@ -117,6 +146,13 @@ template <int I, int N, typename F> __device__ __forceinline__ void static_for(F
 
 // LDS of one work-group (dynamic: more than 64 KiB for the widest panels).  TC = column tiles
 // whose per-wave products are reduced at a time.
+// LDS behind BlkSmem for the STORE_VK tail: the cross products gx[l][j] = V_l^T V_j (l < j) of
+// the blocks' reflectors, later reused for the top row tiles v1[j][l] of V (j >= l); every tile
+// 16 x 16 row-major.  (The tiles of T_p overlay BlkSmem::red, free by then.)
+template <typename T, int NCT> struct BlkTail {
+    T tiles[NCT][NCT][256];
+};
+
 template <typename T, int NCT, int RT, int NW, int TC> struct BlkSmem {
     T part[2][NW][16];               // per-step partial dots of the block's columns
     T rowk[2][16];                   // pivot row k restricted to the block
@@ -130,10 +166,13 @@ template <typename T, int NCT, int RT, int NW, int TC> struct BlkSmem {
     T ybuf[16][NCT * 16 + 1];        // Y = T^T W (or T W) for the trailing tiles
 };
 
-template <typename Tin, typename T, int NCT, int RT, int NW, int TC>
+// q1 == nullptr: R only.  Otherwise VK: q1 receives V (rows x n, ld n) and kout the panel's K
+// (n x n, ld n, at p n n); !VK: q1 receives the explicit Q1.
+template <typename Tin, typename T, int NCT, int RT, int NW, int TC, bool VK = false>
 __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin *__restrict__ X,
                                                  int64_t ldx, T *__restrict__ q1,
-                                                 double *__restrict__ S, int64_t p)
+                                                 double *__restrict__ S, int64_t p,
+                                                 T *__restrict__ kout = nullptr)
 {
     using K = BlkT<T>;
     typedef typename K::acc_t acc_t;
@@ -310,7 +349,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
             // pivot column x (rows > k) and the partial dots with the block's columns; tiles
             // above tile kt hold finished rows (x = 0, no update)
             T xm[RT][4];
-            T d0 = T(0), d1 = T(0);
+            T dacc[4] = {T(0), T(0), T(0), T(0)};      // four independent FMA chains
 #pragma unroll
             for (int rt = 0; rt < RT; ++rt) {
                 const int gt = rt * NW + w;
@@ -318,27 +357,25 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         xm[rt][i] = K::template bcast16<kk>(P[rt][kt][i]);
-                        if (i & 1) d1 = fma(xm[rt][i], P[rt][kt][i], d1);
-                        else d0 = fma(xm[rt][i], P[rt][kt][i], d0);
+                        dacc[i] = fma(xm[rt][i], P[rt][kt][i], dacc[i]);
                     }
                 } else if (gt == kt) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) {
                         const T xv = K::template bcast16<kk>(P[rt][kt][i]);
                         xm[rt][i] = (K::rit(lr, i) > kk) ? xv : T(0);
-                        if (i & 1) d1 = fma(xm[rt][i], P[rt][kt][i], d1);
-                        else d0 = fma(xm[rt][i], P[rt][kt][i], d0);
+                        dacc[i] = fma(xm[rt][i], P[rt][kt][i], dacc[i]);
                     }
                 } else {
 #pragma unroll
                     for (int i = 0; i < 4; ++i) xm[rt][i] = T(0);
                 }
             }
-            const T d = K::sum_xor32(K::sum_xor16(d0 + d1));
+            const T d = K::sum_xor32(K::sum_xor16((dacc[0] + dacc[1]) + (dacc[2] + dacc[3])));
             if (lr == 0) sm.part[par][w][lc] = d;
             __syncthreads();
-            // the waves' partials, all read at once and added pairwise (NW is a power of two);
-            // pc and the pivot row entry of column lc are ready before the norm is
+            // the waves' partials and the pivot row, read together and added pairwise (NW is a
+            // power of two)
             T ps[NW], pp[NW];
 #pragma unroll
             for (int ww = 0; ww < NW; ++ww) {
@@ -346,7 +383,7 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
                 pp[ww] = sm.part[par][ww][lc];
             }
             const T alpha = sm.rowk[par][kk];
-            const T rowc = sm.rowk[par][lc];
+            T rowc = sm.rowk[par][lc];
 #pragma unroll
             for (int h = NW / 2; h >= 1; h /= 2)
 #pragma unroll
@@ -354,14 +391,18 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
                     ps[ww] += ps[ww + h];
                     pp[ww] += pp[ww + h];
                 }
-            const T s2 = ps[0], pc = pp[0];
+            const T s2 = ps[0];
+            T pc = pp[0];
+            // an empty use of pc and rowc here: without it the compiler sinks their reads into
+            // the branch that needs them, after the square root, and pays a second LDS round trip
+            asm volatile("" : "+v"(pc), "+v"(rowc));
             // one reciprocal per step: with r = 1 / (u beta), tau = (beta - alpha)/beta = -u^2 r
             // and the coefficient tau (a_kc + pc/u)/u of column c is -(a_kc u + pc) r
             // Computed without a branch and then selected (s2 = 0: no reflection, tau = 0), so
             // the sum for pc can overlap the square root; the discarded values of that case
             // (a reciprocal of zero) never reach a result.
             const bool live = s2 != T(0);
-            const T nrm = sqrt(alpha * alpha + s2);
+            const T nrm = K::sqrt_pos(fma(alpha, alpha, s2));
             const T bl = (alpha >= T(0)) ? -nrm : nrm;
             const T ul = alpha - bl;
             const T rl = K::rcp(ul * bl);
@@ -414,9 +455,124 @@ __device__ __forceinline__ void factor_blk_panel(int64_t rows, int n, const Tin 
                     S[(p * n + r) * n + c] = (c > r) ? (double)P[rt][ct][i] : ((c == r) ? (double)sm.beta[r] : T(0) /*keep*/);
             }
     if (q1 == nullptr) return;
+    const int nblk = (n + 15) >> 4;
+
+    if constexpr (VK) {
+        static_assert(NCT * NCT <= NW * TC, "the tiles of T_p overlay BlkSmem::red");
+        BlkTail<T, NCT> &tl = *reinterpret_cast<BlkTail<T, NCT> *>(blk_smem_raw + sizeof(sm));
+        T(*tf)[256] = reinterpret_cast<T(*)[256]>(&sm.red[0][0][0]);     // tile (i, j) at tf[i * NCT + j]
+        // acc += A B for 16 x 16 tiles in LDS: A row-major (ld lda); B row-major (ld ldb), or
+        // transposed when BT (element (k, c) of B at b[c * ldb + k])
+        auto tile_mma = [&](acc_t acc, const T *a, int lda, const T *b, int ldb, bool bt) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int kq = 4 * q + lr;
+                const T av = a[lc * lda + kq];
+                const T bv = bt ? b[lc * ldb + kq] : b[kq * ldb + lc];
+                acc = K::mfma(av, bv, acc);
+            }
+            return acc;
+        };
+        // the last block's T (its trailing step did not run)
+        static_for<0, NCT>([&](auto I) {
+            constexpr int kt = decltype(I)::value;
+            if (kt != nblk - 1) return;
+            T V[RT][4];
+            gather_v(I, V);
+            block_products(I, std::integral_constant<int, NCT>{}, std::true_type{}, V);
+            block_t(I);
+        });
+        // V of every block, in place in P (zero in the tiles past n), and stored
+        static_for<0, NCT>([&](auto I) {
+            constexpr int kt = decltype(I)::value;
+            T V[RT][4];
+            if (kt < nblk) {
+                gather_v(I, V);
+            } else {
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) V[rt][i] = T(0);
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) P[rt][kt][i] = V[rt][i];
+        });
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int ct = 0; ct < NCT; ++ct)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = row_of(rt, i), c = 16 * ct + lc;
+                    if (r < nrow && c < n) q1[(prow0 + r) * n + c] = P[rt][ct][i];
+                }
+        // cross products V_l^T V_j, l < j (over the panel's rows, summed over the waves)
+        static_for<0, NCT - 1>([&](auto L) {
+            constexpr int l = decltype(L)::value;
+            if (l + 1 >= nblk) return;
+            T V[RT][4];
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) V[rt][i] = P[rt][l][i];
+            block_products(L, std::integral_constant<int, l + 1>{}, std::false_type{}, V);
+            for (int e = tid; e < (NCT - 1 - l) * 256; e += NT) tl.tiles[l][l + 1 + (e >> 8)][e & 255] = sm.wsum[l + 1 + (e >> 8)][e & 255];
+            __syncthreads();
+        });
+        // T_p tile rows: wave i computes row i (T_p[i][j], j > i, from its own earlier tiles)
+        for (int e = tid; e < nblk * 256; e += NT) {
+            const int i = e >> 8, r = (e >> 4) & 15, c = e & 15;
+            tf[i * NCT + i][e & 255] = sm.tstore[i][r][c];
+        }
+        __syncthreads();
+        if (w < nblk) {
+            const int i = w;
+            for (int j = i + 1; j < nblk; ++j) {
+                acc_t y = acc_t{0, 0, 0, 0};
+                for (int l = i; l < j; ++l) y = tile_mma(y, tf[i * NCT + l], 16, tl.tiles[l][j], 16, false);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tf[i * NCT + j][K::rit(lr, q) * 16 + lc] = y[q];
+                // (the wave reads back what its own lanes wrote: LDS operations of a wave are ordered)
+                acc_t t = acc_t{0, 0, 0, 0};
+                t = tile_mma(t, tf[i * NCT + j], 16, &sm.tstore[j][0][0], 17, false);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) tf[i * NCT + j][K::rit(lr, q) * 16 + lc] = -t[q];
+            }
+        }
+        __syncthreads();
+        // the top row tiles of V (row tile g holds blocks l <= g), in place of the cross products
+        static_for<0, RT>([&](auto RTI) {
+            constexpr int rt = decltype(RTI)::value;
+            const int g = rt * NW + w;
+            if (g < nblk) {
+#pragma unroll
+                for (int l = 0; l < NCT; ++l)
+                    if (l <= g)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) tl.tiles[g][l][K::rit(lr, q) * 16 + lc] = P[rt][l][q];
+            }
+        });
+        __syncthreads();
+        // K = T_p V1^T: tile (i, j) = sum_{l=i..j} T_p[i][l] (V1^T)[l][j], (V1^T)[l][j] = v1[j][l]^T
+        T *kp = kout + p * (int64_t)n * n;
+        for (int tt = w; tt < NCT * NCT; tt += NW) {
+            const int i = tt / NCT, j = tt - i * NCT;
+            if (i >= nblk || j >= nblk) continue;
+            acc_t acc = acc_t{0, 0, 0, 0};
+            if (i <= j)
+                for (int l = i; l <= j; ++l) acc = tile_mma(acc, tf[i * NCT + l], 16, tl.tiles[j][l], 16, true);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int r = 16 * i + K::rit(lr, q), c = 16 * j + lc;
+                if (r < n && c < n) kp[(int64_t)r * n + c] = acc[q];
+            }
+        }
+        return;
+    }
 
     // ---- explicit Q1 = H_1 ... H_n [I; 0], in place, block by block from the last -----------
-    const int nblk = (n + 15) >> 4;
     static_for<0, NCT>([&](auto I) {
         constexpr int kt = NCT - 1 - decltype(I)::value;
         if (kt >= nblk) return;

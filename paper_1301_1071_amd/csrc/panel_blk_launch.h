@@ -18,28 +18,43 @@ template <typename T, int NCT> struct BlkShape {
     static constexpr int TC = (NCT <= 2) ? NCT : 2;
     static constexpr int B = NW * RT * 16;
     static constexpr size_t LDS = sizeof(BlkSmem<T, NCT, RT, NW, TC>);
+    // with the STORE_VK tail (n <= 64)
+    static constexpr size_t LDS_VK = LDS + sizeof(blkpanel::BlkTail<T, NCT>);
 };
 
-template <typename Tin, typename T, int NCT>
+// VK: kout != nullptr selects the STORE_VK tail (q1 receives V, kout the panels' K); otherwise
+// q1 receives the explicit Q1 (or nothing when null).
+template <typename Tin, typename T, int NCT, bool VK>
 __global__ void __launch_bounds__((NCT <= 2) ? 256 : 512, (NCT <= 2) ? 2 : 1)
 k_factor_blk(int64_t rows, int n, const Tin *__restrict__ X, int64_t ldx, T *__restrict__ q1,
-             double *__restrict__ S)
+             double *__restrict__ S, T *__restrict__ kout)
 {
     using C = BlkShape<T, NCT>;
-    blkpanel::factor_blk_panel<Tin, T, NCT, C::RT, C::NW, C::TC>(rows, n, X, ldx, q1, S,
-                                                                blockIdx.x);
+    blkpanel::factor_blk_panel<Tin, T, NCT, C::RT, C::NW, C::TC, VK>(rows, n, X, ldx, q1, S,
+                                                                    blockIdx.x, kout);
 }
 
 template <typename Tin, typename T, int NCT>
 hipError_t factor_blk_launch(int64_t rows, int64_t n, const void *X, int64_t ldx, void *q1,
-                             double *S, hipStream_t st)
+                             double *S, hipStream_t st, void *kout = nullptr)
 {
     using C = BlkShape<T, NCT>;
     const int64_t panels = ceil_div(rows, C::B);
-    hipError_t e = ensure_dynamic_lds((const void *)k_factor_blk<Tin, T, NCT>, C::LDS);
+    if constexpr (NCT <= 4) {
+        if (kout) {
+            hipError_t e = ensure_dynamic_lds((const void *)k_factor_blk<Tin, T, NCT, true>, C::LDS_VK);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_factor_blk<Tin, T, NCT, true>), dim3((unsigned)panels),
+                               dim3(C::NW * 64), C::LDS_VK, st, rows, (int)n, (const Tin *)X, ldx,
+                               (T *)q1, S, (T *)kout);
+            return hipGetLastError();
+        }
+    }
+    if (kout) return hipErrorInvalidValue;
+    hipError_t e = ensure_dynamic_lds((const void *)k_factor_blk<Tin, T, NCT, false>, C::LDS);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_factor_blk<Tin, T, NCT>), dim3((unsigned)panels), dim3(C::NW * 64),
-                       C::LDS, st, rows, (int)n, (const Tin *)X, ldx, (T *)q1, S);
+    hipLaunchKernelGGL((k_factor_blk<Tin, T, NCT, false>), dim3((unsigned)panels), dim3(C::NW * 64),
+                       C::LDS, st, rows, (int)n, (const Tin *)X, ldx, (T *)q1, S, (T *)nullptr);
     return hipGetLastError();
 }
 

@@ -57,7 +57,9 @@ struct Level {
     int64_t panels = 0;   // number of row panels (map tasks)
     int b = 0;            // panel height
     int dtype = F64;      // arithmetic of the panel work at this level
-    size_t q1 = 0;        // offset of explicit Q1 panels (rows x n, ld n), 0 if not kept
+    size_t q1 = 0;        // offset of explicit Q1 panels (rows x n, ld n), 0 if not kept; with
+                          // kv != 0 the panels' reflectors V instead
+    size_t kv = 0;        // offset of the panels' K (panels x n x n): Q1_p = [I; 0] - V_p K_p
     size_t s = 0;         // offset of the stacked R output (panels*n x n, FP64)
     size_t x = 0;         // offset of this level's Q (rows x k, FP64), levels >= 1 only
     size_t gpanel = 0;    // offset of global scratch panels (panels tall for LDS), 0 if unused
@@ -97,18 +99,21 @@ hipError_t launch_factor(int in_dtype, int dtype, int64_t rows, int64_t n, int b
                          hipStream_t st);
 
 // ---- launchers (panel_blk.hip): blocked register panels, the default for every level --------
-// Panel height of the blocked kernel for (n, dtype): 384 rows for n <= 32, 256 rows above.
+// Panel height of the blocked kernel for (n, dtype): 384 rows for n <= 32, 512 for n <= 64, 256
+// above.  q1 == nullptr: R only; kout != nullptr (n <= 64): q1 receives V and kout the panels' K
+// (element type dtype, panels x n x n); otherwise q1 receives the explicit Q1.
 int reg_panel_rows(int64_t n, int dtype);
 hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, const void *X,
-                             int64_t ldx, void *q1, double *S, hipStream_t st);
+                             int64_t ldx, void *q1, double *S, void *kout, hipStream_t st);
 
 // ---- launchers (apply_mfma.hip): step 3 on the matrix cores --------------------------------
 // out = Q1 * W per panel: panel p (rows [p b, p b + b)) uses W rows [p*wstride, p*wstride + n).
-// Columns [0, k0) of the product go to out0 (ld0), columns [k0, k) to out1 (ld1).
+// Columns [0, k0) of the product go to out0 (ld0), columns [k0, k) to out1 (ld1).  With kmat
+// (n <= 64) q1 holds the reflectors V and kmat the panels' K (Q1 = [I; 0] - V K).
 hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                              const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
                              void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
-                             hipStream_t st);
+                             const void *kmat, hipStream_t st);
 
 // General tall product on the same kernel: out = X * W (X: rows x n, row stride ldq) panel by
 // panel (panel p of b rows uses W rows [p*wstride, +n)); accumulate != 0 adds to out.
