@@ -30,6 +30,11 @@
  *     orthonormal columns, R is n x n upper triangular (strict lower triangle written as 0).
  *   - Supported: 1 <= n <= TSQR_NMAX, m >= n.  Values must be well inside the floating-point
  *     range (|a_ij| < 1e150 in FP64, < 1e17 in FP32): column norms are formed without scaling.
+ *     Widths 128 < n <= TSQR_NMAX run the wide path: every level of the tree factors panels of
+ *     4 n rows held in global workspace (a quarter of the rows per level, Sec. III-C), and step 3
+ *     runs in column chunks of 128.  The adjoints, the comparison methods and the metrics keep
+ *     n <= TSQR_NMAX_SMALL (their n x n work runs in one work-group's LDS); the refined
+ *     precision form and the batched form keep n <= 64.
  */
 #ifndef TSQR_H
 #define TSQR_H
@@ -42,12 +47,13 @@ extern "C" {
 #endif
 
 #define TSQR_ABI_VERSION 1
-#define TSQR_NMAX 128
+#define TSQR_NMAX 512
+#define TSQR_NMAX_SMALL 128
 
 typedef enum {
     TSQR_OK = 0,
     TSQR_ERR_INVALID_ARG = 1, /* NULL pointer, ld < n, m <= 0, n <= 0, bad enum */
-    TSQR_ERR_SHAPE = 2,       /* m < n or n > TSQR_NMAX */
+    TSQR_ERR_SHAPE = 2,       /* m < n, or n above the entry point's limit */
     TSQR_ERR_WORKSPACE = 3,   /* ws == NULL or ws_bytes too small */
     TSQR_ERR_UNSUPPORTED = 4, /* option combination not implemented */
     TSQR_ERR_HIP = 5          /* a HIP launch/runtime error */
@@ -162,8 +168,9 @@ tsqr_status tsqr_svd_f32(int64_t m, int64_t n, const float *A, int64_t lda, floa
  * be kept.  Closed form (not in the paper; Walter & Lehmann 2018, Seeger et al. 2017):
  *     M = R triu(dR)^T - dQ^T Q,   dA = (dQ + Q copyltu(M)) R^{-T},
  *     copyltu(M) = tril(M) + tril(M, -1)^T.
- * FP64 only (opts->precision must be TSQR_FP64).  Workspace: tsqr_workspace_bytes with
- * TSQR_OP_QR_BACKWARD.  d_info as for tsqr_qr, or -3 if R has a zero diagonal entry.
+ * FP64 only (opts->precision must be TSQR_FP64), n <= TSQR_NMAX_SMALL.  Workspace:
+ * tsqr_workspace_bytes with TSQR_OP_QR_BACKWARD.  d_info as for tsqr_qr, or -3 if R has a zero
+ * diagonal entry.
  */
 tsqr_status tsqr_qr_backward(int64_t m, int64_t n, const double *A, int64_t lda,
                              const double *dQ, int64_t lddq, const double *dR, int64_t lddr,
@@ -178,7 +185,7 @@ tsqr_status tsqr_qr_backward(int64_t m, int64_t n, const double *A, int64_t lda,
  *     K = F o (V^T dV - dV^T V),
  *     dA = U (J S + diag(dS) + S K) V^T + (dU - U (U^T dU)) S^{-1} V^T.
  * The result follows the gauge of tsqr_svd.  d_info as for tsqr_svd, or -3 if two singular
- * values coincide or one is zero.  Workspace: TSQR_OP_SVD_BACKWARD.
+ * values coincide or one is zero.  n <= TSQR_NMAX_SMALL.  Workspace: TSQR_OP_SVD_BACKWARD.
  */
 tsqr_status tsqr_svd_backward(int64_t m, int64_t n, const double *A, int64_t lda,
                               const double *dU, int64_t lddu, const double *dS,
@@ -276,7 +283,8 @@ const char *tsqr_profile_class_name(int32_t c);
  * Both form Q = A R^{-1} with the explicit inverse of R (Sec. II-C), which is not backward
  * stable: ||Q^T Q - I|| grows with kappa(A) (Cholesky QR: with kappa(A)^2).  refine = 1 repeats
  * the same QR once on the computed Q (iterative refinement, Sec. I): Q = Q1 R2^{-1}, R = R2 R1.
- * FP64 only (opts->precision must be TSQR_FP64).  A, Q: m x n; R: n x n upper triangular.
+ * FP64 only (opts->precision must be TSQR_FP64), n <= TSQR_NMAX_SMALL.  A, Q: m x n; R: n x n
+ * upper triangular.
  * ------------------------------------------------------------------------------------------ */
 typedef enum { TSQR_METHOD_CHOLQR = 1, TSQR_METHOD_INDIRECT = 2 } tsqr_method;
 tsqr_status tsqr_indirect_workspace_bytes(int32_t method, int32_t refine, int64_t m, int64_t n,
@@ -294,7 +302,8 @@ tsqr_status tsqr_qr_indirect(int32_t method, int32_t refine, int64_t m, int64_t 
  *   compensated dot product);  mode 2: G = X^T X.
  * X, A: m x n device matrices (row-major, ldx, lda); G: n x n device (ld n, symmetric).  The
  * caller takes the 2-norm of the small G (||Q^T Q - I||_2 = ||G||_2 for mode 0,
- * ||A - QR||_2 = sqrt(lambda_max(G)) for mode 1).  ws: tsqr_metric_workspace_bytes.
+ * ||A - QR||_2 = sqrt(lambda_max(G)) for mode 1).  n <= TSQR_NMAX_SMALL.
+ * ws: tsqr_metric_workspace_bytes.
  * ------------------------------------------------------------------------------------------ */
 tsqr_status tsqr_metric_workspace_bytes(int64_t m, int64_t n, size_t *bytes);
 tsqr_status tsqr_metric_gram(int32_t mode, int64_t m, int64_t n, const double *X, int64_t ldx,

@@ -133,7 +133,14 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         // panel (b >= 2n); a short FP32 stack that they would not shrink uses one LDS (or
         // global-memory) panel instead
         const bool shrinks = ceil_div(rows, breg) * n < rows;
-        if (req == 0 && (rows <= breg || (shrinks && (lv.dtype == F64 || rows > 8 * n)))) {
+        if (n > kNmaxPad) {
+            // the wide path: global-scratch panels of 4 n rows (explicit heights allowed), each
+            // level a quarter of the one below
+            lv.reg = false;
+            const int64_t want = req ? req : 4 * n;
+            lv.b = (int)(want < rows ? want : rows);
+            lv.global = true;
+        } else if (req == 0 && (rows <= breg || (shrinks && (lv.dtype == F64 || rows > 8 * n)))) {
             // default: register-resident panels of the register kernel's height
             lv.reg = true;
             lv.global = false;
@@ -376,6 +383,7 @@ tsqr_status build_indirect_layout(int method, int refine, int64_t m, int64_t n, 
     if (method != TSQR_METHOD_CHOLQR && method != TSQR_METHOD_INDIRECT) return TSQR_ERR_INVALID_ARG;
     if (refine != 0 && refine != 1) return TSQR_ERR_INVALID_ARG;
     if (o && o->precision != TSQR_FP64) return TSQR_ERR_UNSUPPORTED;
+    if (n > TSQR_NMAX_SMALL) return TSQR_ERR_SHAPE;     // Cholesky and inverse in LDS
     tsqr_status s = build_plan(OP_R, m, n, F64, o, false, false, L.pr);
     if (s != TSQR_OK) return s;
     size_t off = align_up(L.pr.total);
@@ -433,6 +441,7 @@ struct BwdLayout {
 tsqr_status build_bwd_layout(bool svd, int64_t m, int64_t n, const tsqr_opts *o, BwdLayout &bl)
 {
     if (o && o->precision != TSQR_FP64) return TSQR_ERR_UNSUPPORTED;
+    if (n > TSQR_NMAX_SMALL) return TSQR_ERR_SHAPE;     // the n x n adjoint work in LDS
     tsqr_status s = svd ? build_plan(OP_SVD, m, n, F64, o, false, true, bl.fwd)
                         : build_plan(OP_QR, m, n, F64, o, true, false, bl.fwd);
     if (s != TSQR_OK) return s;

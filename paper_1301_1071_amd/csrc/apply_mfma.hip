@@ -94,7 +94,21 @@ hipError_t launch_apply_vk(int q_dtype, int out_dtype, int64_t rows, int64_t n, 
                           int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
                           int64_t ld1, int accumulate, const void *kmat, hipStream_t st)
 {
-    if (n > 4 * kMaxKC) return hipErrorInvalidValue;
+    if (n > 4 * kMaxKC) {
+        // wide n: the product runs in K chunks of 4 kMaxKC columns of Q1 (rows of W), the
+        // first overwriting the output and the others adding to it
+        if (kmat || n > kNmaxWide) return hipErrorInvalidValue;
+        const size_t es = (q_dtype == F64) ? sizeof(double) : sizeof(float);
+        for (int64_t c0 = 0; c0 < n; c0 += 4 * kMaxKC) {
+            const int64_t nc = std::min<int64_t>(4 * kMaxKC, n - c0);
+            hipError_t e = launch_apply_vk(q_dtype, out_dtype, rows, nc, b,
+                                           (const char *)q1 + es * c0, ldq, W + c0 * ldw, ldw,
+                                           wstride, k, out0, ld0, k0, out1, ld1,
+                                           (accumulate || c0 > 0) ? 1 : 0, nullptr, st);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     if (kmat && (n > 64 || accumulate)) return hipErrorInvalidValue;
     if (q_dtype == F64) {
         if (out_dtype == F64)
@@ -115,7 +129,6 @@ hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n,
                             int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
                             int64_t ld1, int accumulate, hipStream_t st)
 {
-    if (n > 4 * kMaxKC) return hipErrorInvalidValue;
     return launch_apply_vk(q_dtype, out_dtype, rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0,
                            k0, out1, ld1, accumulate, nullptr, st);
 }

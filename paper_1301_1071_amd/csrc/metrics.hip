@@ -148,7 +148,7 @@ extern "C" {
 tsqr_status tsqr_metric_workspace_bytes(int64_t m, int64_t n, size_t *bytes)
 {
     if (!bytes || m <= 0 || n <= 0) return TSQR_ERR_INVALID_ARG;
-    if (n > TSQR_NMAX) return TSQR_ERR_SHAPE;
+    if (n > TSQR_NMAX_SMALL) return TSQR_ERR_SHAPE;
     *bytes = sizeof(double) * 2 * (size_t)metric_blocks(m) * (size_t)(n * (n + 1) / 2);
     return TSQR_OK;
 }
@@ -160,7 +160,7 @@ tsqr_status tsqr_metric_gram(int32_t mode, int64_t m, int64_t n, const double *X
     if (mode < 0 || mode > 2 || !X || !G || m <= 0 || n <= 0 || ldx < n)
         return TSQR_ERR_INVALID_ARG;
     if (mode == 1 && (!A || !B || lda < n || ldb < n)) return TSQR_ERR_INVALID_ARG;
-    if (n > TSQR_NMAX) return TSQR_ERR_SHAPE;
+    if (n > TSQR_NMAX_SMALL) return TSQR_ERR_SHAPE;
     size_t need = 0;
     tsqr_metric_workspace_bytes(m, n, &need);
     if (!ws || ws_bytes < need) return TSQR_ERR_WORKSPACE;

@@ -1,10 +1,12 @@
-// Panel kernels with the row panel resident in LDS (general n <= TSQR_NMAX, FP64 or FP32).
+// Panel kernels with the row panel resident in LDS or, for panels too tall or too wide for LDS, in
+// a global scratch panel (general n <= TSQR_NMAX, FP64 or FP32).
 //
 // Step 1 of direct TSQR (Sec. III-B): one work-group factors one row panel A_p = Q1_p R_p with
 // Householder reflections (Sec. III-A), writes R_p into the stacked-R buffer (block p = rows
 // [p n, p n + n), the ordering the step-2 reduce task relies on) and, when Q is wanted, forms
 // Q1_p = H_1 ... H_n [I; 0] explicitly so that step 3 is a plain product Q1_p * Q2_p.  Used for
-// explicitly requested panel heights (tsqr_opts.panel_rows) and short FP32 stacks.
+// explicitly requested panel heights (tsqr_opts.panel_rows), short FP32 stacks and every level
+// of the wide path (n > 128), whose panels live in global scratch.
 //
 // Householder convention: for column k, x = A[k:, k], alpha = x_0, s2 = ||x_{1:}||^2;
 // beta = -sign(alpha) sqrt(alpha^2 + s2) (sign(0) = +1), tau = (beta - alpha) / beta and
@@ -17,22 +19,22 @@ namespace tsqr {
 namespace {
 
 constexpr int kLdsBudget = 150 * 1024;   // bytes of LDS used by one panel work-group
-constexpr int kNpad = 128;               // column capacity of the small LDS arrays
 
 template <typename T>
 __device__ __forceinline__ T shfl_xor(T v, int mask) { return __shfl_xor(v, mask, 64); }
 
-template <typename Tin, typename T>
+// NPAD: column capacity of the small per-column LDS arrays (128, or 512 for the wide path)
+template <typename Tin, typename T, int NPAD>
 __global__ void __launch_bounds__(kThreads)
 k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__restrict__ X,
              int64_t ldx, T *__restrict__ q1, double *__restrict__ S, T *gpanel)
 {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    __shared__ T red[4 * kNpad];                   // per-wave partial dots
-    __shared__ T rowk[kNpad];                      // row k of the panel, published per step
-    __shared__ T s_tau[kNpad];
-    __shared__ T s_umk[kNpad];                     // alpha - beta
-    __shared__ T s_beta[kNpad];                    // R_kk
+    __shared__ T red[4 * NPAD];                   // per-wave partial dots
+    __shared__ T rowk[NPAD];                      // row k of the panel, published per step
+    __shared__ T s_tau[NPAD];
+    __shared__ T s_umk[NPAD];                     // alpha - beta
+    __shared__ T s_beta[NPAD];                    // R_kk
     // the panel: n columns of ldp rows (column-major), in LDS or, for panels too tall for LDS,
     // in a global scratch panel (one per work-group)
     T *P = gpanel ? gpanel + (size_t)blockIdx.x * n * ldp : reinterpret_cast<T *>(smem_raw);
@@ -73,13 +75,13 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
             }
             for (int off = NC; off < 64; off <<= 1) d += shfl_xor(d, off);
             if (g == 0 && c < n) {
-                red[w * kNpad + c] = d;
+                red[w * NPAD + c] = d;
                 if (w == 0) rowk[c] = P[(size_t)c * ldp + k];
             }
         }
         __syncthreads();
         const T alpha = rowk[k];
-        const T s2 = red[k] + red[kNpad + k] + red[2 * kNpad + k] + red[3 * kNpad + k];
+        const T s2 = red[k] + red[NPAD + k] + red[2 * NPAD + k] + red[3 * NPAD + k];
         T tau = T(0), umk = T(0), beta = alpha;
         if (s2 != T(0)) {
             const T nrm = sqrt(alpha * alpha + s2);
@@ -93,7 +95,7 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
             for (int ps = 0; ps < npass; ++ps) {
                 const int c = cl + ps * NC;
                 if (c > k && c < n) {
-                    const T pcs = red[c] + red[kNpad + c] + red[2 * kNpad + c] + red[3 * kNpad + c];
+                    const T pcs = red[c] + red[NPAD + c] + red[2 * NPAD + c] + red[3 * NPAD + c];
                     const T wc = rowk[c] + inv * pcs;          // v^T A[k:, c]
                     const T coef = tau * wc * inv;
                     T *pc = P + (size_t)c * ldp;
@@ -128,7 +130,7 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
                 for (int i = i0 + g; i < r1; i += G) d = fma(xk[i], pc[i], d);
             }
             for (int off = NC; off < 64; off <<= 1) d += shfl_xor(d, off);
-            if (g == 0 && c < n) red[w * kNpad + c] = d;
+            if (g == 0 && c < n) red[w * NPAD + c] = d;
         }
         __syncthreads();
         if (tau != T(0)) {
@@ -136,7 +138,7 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
                 const int c = cl + ps * NC;
                 if (c > k && c < n) {
                     // row k of column c is zero here (cleared when column c was formed)
-                    const T wc = inv * (red[c] + red[kNpad + c] + red[2 * kNpad + c] + red[3 * kNpad + c]);
+                    const T wc = inv * (red[c] + red[NPAD + c] + red[2 * NPAD + c] + red[3 * NPAD + c]);
                     const T coef = tau * wc * inv;
                     T *pc = P + (size_t)c * ldp;
                     for (int i = i0 + g; i < r1; i += G) pc[i] = fma(-coef, xk[i], pc[i]);
@@ -174,7 +176,8 @@ hipError_t factor_impl(int64_t rows, int64_t n, int b, const void *X, int64_t ld
                        double *S, void *gpanel, hipStream_t st)
 {
     const size_t lds = gpanel ? 0 : lds_bytes<T>((int)n, b);
-    auto kern = k_factor_lds<Tin, T>;
+    if (n > kNmaxWide || (n > kNmaxPad && !gpanel)) return hipErrorInvalidValue;
+    auto kern = (n > kNmaxPad) ? k_factor_lds<Tin, T, kNmaxWide> : k_factor_lds<Tin, T, kNmaxPad>;
     hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
     if (e != hipSuccess) return e;
     const int64_t panels = ceil_div(rows, b);

@@ -60,6 +60,9 @@ __device__ __forceinline__ double group16_sum(double v)
     return dpp_d<0x150>(v);       // row_newbcast:0
 }
 
+// NPAD: column capacity (128, or 512 for the wide path, whose Jacobi columns are re-read from
+// memory for the rotation instead of being kept in registers)
+template <int NPAD>
 __global__ void __launch_bounds__(kSvdThreads)
 k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *__restrict__ Rf,
            int64_t ldr, double *__restrict__ Wtop, int k, int want_q, int want_u,
@@ -68,10 +71,12 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
            int32_t *__restrict__ info, int keep_info)
 {
     extern __shared__ __align__(16) double sm[];
-    __shared__ double d_s[kNmaxPad];
-    __shared__ double s_sv[kNmaxPad];
-    __shared__ double s_sg[kNmaxPad];
-    __shared__ int perm[kNmaxPad];
+    constexpr int NJ = NPAD / 16;                 // 16-row chunks of a column
+    constexpr bool kCache = NJ <= 8;              // columns held in registers between the passes
+    __shared__ double d_s[NPAD];
+    __shared__ double s_sv[NPAD];
+    __shared__ double s_sg[NPAD];
+    __shared__ int perm[NPAD];
     __shared__ int s_zero, s_nonfinite, s_rot;
 
     const int tid = threadIdx.x;
@@ -127,17 +132,18 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
                     const int p = min(a, bq), q = max(a, bq);
                     if (q >= n) continue;
                     double *gp = gG + (int64_t)p * n, *gq = gG + (int64_t)q * n;
-                    double xp[kNmaxPad / 16], xq[kNmaxPad / 16];
+                    double xp[kCache ? NJ : 1], xq[kCache ? NJ : 1];
                     double al = 0.0, be = 0.0, ga = 0.0;
 #pragma unroll
-                    for (int j = 0; j < kNmaxPad / 16; ++j) {
+                    for (int j = 0; j < NJ; ++j) {
                         if (j >= nj) break;                    // uniform: chunks past n
                         const int i = gl + 16 * j;
-                        xp[j] = (i < n) ? gp[i] : 0.0;
-                        xq[j] = (i < n) ? gq[i] : 0.0;
-                        al = fma(xp[j], xp[j], al);
-                        be = fma(xq[j], xq[j], be);
-                        ga = fma(xp[j], xq[j], ga);
+                        const double a = (i < n) ? gp[i] : 0.0;
+                        const double c = (i < n) ? gq[i] : 0.0;
+                        if constexpr (kCache) { xp[j] = a; xq[j] = c; }
+                        al = fma(a, a, al);
+                        be = fma(c, c, be);
+                        ga = fma(a, c, ga);
                     }
                     al = group16_sum(al);
                     be = group16_sum(be);
@@ -150,12 +156,14 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
                         const double sn = cs * tt;
                         double *vp = gV + (int64_t)p * n, *vq = gV + (int64_t)q * n;
 #pragma unroll
-                        for (int j = 0; j < kNmaxPad / 16; ++j) {
+                        for (int j = 0; j < NJ; ++j) {
                             if (j >= nj) break;
                             const int i = gl + 16 * j;
                             if (i < n) {
-                                gp[i] = cs * xp[j] - sn * xq[j];
-                                gq[i] = sn * xp[j] + cs * xq[j];
+                                const double a = kCache ? xp[kCache ? j : 0] : gp[i];
+                                const double c = kCache ? xq[kCache ? j : 0] : gq[i];
+                                gp[i] = cs * a - sn * c;
+                                gq[i] = sn * a + cs * c;
                                 const double yp = vp[i], yq = vq[i];
                                 vp[i] = cs * yp - sn * yq;
                                 vq[i] = sn * yp + cs * yq;
@@ -224,13 +232,15 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
     const size_t need = svd ? 2 * sizeof(double) * (size_t)n * n : 0;
     const int use_lds = (svd && need <= (size_t)kSmallLdsLimit) ? 1 : 0;
     const size_t lds = use_lds ? need : 0;
-    hipError_t e = ensure_dynamic_lds((const void *)k_finalize, lds);
+    if (n > kNmaxWide) return hipErrorInvalidValue;
+    auto kern = (n > kNmaxPad) ? k_finalize<kNmaxWide> : k_finalize<kNmaxPad>;
+    hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
     if (e != hipSuccess) return e;
     // one 16-lane group per column pair of a Jacobi round, whole waves, so that each round's
     // barrier waits only for waves that have work
     const int64_t pairs = (n + (n & 1)) / 2;
     const int threads = (int)std::min<int64_t>(kSvdThreads, std::max<int64_t>(64, (16 * pairs + 63) / 64 * 64));
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(threads), lds, st, (int)n, Rt, R,
+    hipLaunchKernelGGL(kern, dim3(1), dim3(threads), lds, st, (int)n, Rt, R,
                        Rf, ldr, Wtop, k, want_q, want_u, S, Sf, V, Vf, ldv, G, Vw, use_lds, info,
                        keep_info);
     return hipGetLastError();

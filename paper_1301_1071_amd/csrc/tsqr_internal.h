@@ -12,7 +12,8 @@ namespace tsqr {
 constexpr int kThreads = 256;          // work-group size of the panel kernels (4 waves of 64)
 constexpr int kMaxLevels = 48;         // recursion depth limit of the in-HBM tree
 constexpr size_t kAlign = 256;         // workspace sub-buffer alignment
-constexpr int kNmaxPad = 128;          // column capacity of per-column LDS arrays (>= TSQR_NMAX)
+constexpr int kNmaxPad = 128;          // column capacity of per-column LDS arrays, n <= 128
+constexpr int kNmaxWide = 512;         // the same for the wide path (128 < n <= TSQR_NMAX)
 
 // ---- optional per-launch timing (benchmarks): HIP event pairs on the launch stream (api.hip)
 enum ProfClass {

@@ -53,7 +53,8 @@ def test_workspace_query():
     st, bs = _ws("svd", 100_000, 10)
     assert st == 0 and bs > b1          # Q and U carried down the tree
     assert _ws("qr", 5, 10)[0] == 2     # m < n
-    assert _ws("qr", 1000, 129)[0] == 2  # n > TSQR_NMAX
+    assert _ws("qr", 1000, 513)[0] == 2  # n > TSQR_NMAX
+    assert _ws("qr", 1000, 512)[0] == 0  # the wide path
     assert _ws("qr", 0, 10)[0] == 1
     assert _ws("qr", 1000, 0)[0] == 1
     assert lib().tsqr_workspace_bytes(9, 10, 1, None, ctypes.byref(ctypes.c_size_t())) == 1
@@ -62,7 +63,7 @@ def test_workspace_query():
     assert st == 0 and bq >= b1 + 100_000 * 10 * 8
     st, bsv = _ws("svd_backward", 100_000, 10)
     assert st == 0 and bsv >= 100_000 * 10 * 8
-    assert _ws("qr_backward", 1000, 129)[0] == 2
+    assert _ws("qr_backward", 1000, 129)[0] == 2          # n > TSQR_NMAX_SMALL
     assert _ws("svd_backward", 5, 10)[0] == 2
     assert _ws("qr_backward", 1000, 10, make_opts("fp32"))[0] == 4      # FP64 only
 
@@ -103,7 +104,7 @@ def test_entry_points_reject_bad_arguments_without_gpu():
     assert L.tsqr_r(100, 10, FAKE, 10, FAKE, 9, FAKE, 1 << 30, info, None, None) == 1
     # shapes
     assert L.tsqr_qr(5, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 1 << 30, info, None, None) == 2
-    assert L.tsqr_r(1000, 200, FAKE, 200, FAKE, 200, FAKE, 1 << 30, info, None, None) == 2
+    assert L.tsqr_r(1000, 600, FAKE, 600, FAKE, 600, FAKE, 1 << 30, info, None, None) == 2
     # workspace missing or too small
     assert L.tsqr_qr(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, None, 1 << 30, info, None, None) == 3
     assert L.tsqr_qr(100, 10, FAKE, 10, FAKE, 10, FAKE, 10, FAKE, 16, info, None, None) == 3
@@ -255,3 +256,23 @@ def test_svd_workspace_covers_both_outputs_and_refined_forms():
     nb = ctypes.c_size_t()
     assert lib().tsqr_metric_workspace_bytes(1000, 10, ctypes.byref(nb)) == 0 and nb.value > 0
     assert lib().tsqr_metric_workspace_bytes(1000, 129, ctypes.byref(nb)) == 2
+
+
+@pytest.mark.parametrize("n", [129, 256, 512])
+def test_wide_plan_quarters_each_level(n):
+    """Widths above 128 factor panels of 4 n rows at every level (Sec. III-C recursion), so each
+    level's stacked R holds a quarter of the rows below it; the top is one panel; every level
+    of the tree is a whole number of n-row blocks."""
+    from paper_1301_1071_amd._lib import plan_levels
+    m = 200 * n
+    lv = plan_levels("qr", m, n)
+    assert lv[0] == (m, 4 * n)
+    for (rows, b), (rows_next, _) in zip(lv, lv[1:]):
+        assert b == min(4 * n, rows)
+        assert rows_next == -(-rows // b) * n and rows_next < rows
+    assert lv[-1][1] == lv[-1][0]
+    for op in ("r", "qr", "svd"):
+        st, nbytes = _ws(op, m, n)
+        assert st == 0 and nbytes > 0
+    assert _ws("qr", m, n, make_opts("fp32_refined"))[0] == 4
+    assert _ws("svd_backward", m, n)[0] == 2
