@@ -72,8 +72,21 @@ typedef struct {
     int32_t struct_size; /* sizeof(tsqr_opts) */
     int32_t precision;   /* tsqr_precision */
     int32_t panel_rows;  /* 0 = library default for (n, precision); otherwise a supported height */
-    int32_t flags;       /* reserved, must be 0 */
+    int32_t flags;       /* 0 or TSQR_FLAG_REUSE_OUTPUT */
 } tsqr_opts;
+
+/* Keep the level-0 panel factors (Q1_i, or their reflectors) in the output buffer that step 3
+ * overwrites (Q; U for tsqr_svd without Q) instead of in the workspace, which then shrinks by
+ * m x n elements: A, Q and the workspace of a 600,000,000 x 25 QR fit in one GPU's HBM.  Step 3
+ * then covers all output columns of a row block in one work-group, which reads the block's
+ * factors before it writes the block.  Needs that output contiguous (ldq == n, or ldu == n;
+ * TSQR_ERR_INVALID_ARG otherwise) and supports n <= 128 with at most 128 output columns (n for
+ * tsqr_qr; n for tsqr_svd without Q, 2 n with Q) when the level-0 arithmetic has the input's
+ * element type (not TSQR_FP32 on FP64 input); other cases return TSQR_ERR_UNSUPPORTED, from the
+ * call and from the workspace query (which for TSQR_FP32 with this flag assumes FP32 input and,
+ * for TSQR_OP_SVD, sizes the layouts the flag supports).  Ignored where no Q is formed (tsqr_r,
+ * the refined precision form) and by the adjoints. */
+#define TSQR_FLAG_REUSE_OUTPUT 1
 
 /* Operation codes for tsqr_workspace_bytes. */
 typedef enum {

@@ -71,12 +71,15 @@ class Opts(ctypes.Structure):
                 ("panel_rows", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
-def make_opts(precision: str = "fp64", panel_rows: int = 0) -> Opts:
+FLAG_REUSE_OUTPUT = 1
+
+
+def make_opts(precision: str = "fp64", panel_rows: int = 0, reuse_output: bool = False) -> Opts:
     o = Opts()
     o.struct_size = ctypes.sizeof(Opts)
     o.precision = PRECISION[precision]
     o.panel_rows = int(panel_rows)
-    o.flags = 0
+    o.flags = FLAG_REUSE_OUTPUT if reuse_output else 0
     return o
 
 

@@ -80,7 +80,7 @@ tsqr_status validate_opts(const tsqr_opts *o, int64_t n)
     if (!o) return TSQR_OK;
     if (o->struct_size != (int32_t)sizeof(tsqr_opts)) return TSQR_ERR_INVALID_ARG;
     if (o->precision < TSQR_FP64 || o->precision > TSQR_FP32) return TSQR_ERR_INVALID_ARG;
-    if (o->flags != 0) return TSQR_ERR_INVALID_ARG;
+    if ((o->flags & ~TSQR_FLAG_REUSE_OUTPUT) != 0) return TSQR_ERR_INVALID_ARG;
     if (o->panel_rows < 0) return TSQR_ERR_INVALID_ARG;
     if (o->panel_rows > 0 && (o->panel_rows < n || o->panel_rows > (1 << 16)))
         return TSQR_ERR_INVALID_ARG;
@@ -113,6 +113,15 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
     const bool refined = (pl.precision == TSQR_FP32_REFINED) && op != OP_R;
     const bool need_q = (op != OP_R) && !refined;
     pl.k = need_q ? (int)((want_q ? n : 0) + (want_u ? n : 0)) : (refined && op == OP_SVD ? (int)n : 0);
+    if (need_q && o && (o->flags & TSQR_FLAG_REUSE_OUTPUT)) {
+        // the output is rewritten row block by row block while step 3 reads the same rows, so
+        // one work-group must cover all of a panel's columns, in one chunk of K, in a buffer of
+        // the level-0 element size
+        if (n > kNmaxPad || elem_size(dtype0) != elem_size(in_dtype) ||
+            !apply_one_slice_ok(dtype0, in_dtype, n, pl.k))
+            return TSQR_ERR_UNSUPPORTED;
+        pl.reuse_output = true;
+    }
 
     size_t off = kAlign;   // offset 0 is reserved so that 0 means "not allocated"
     auto take = [&](size_t bytes) {
@@ -158,7 +167,7 @@ tsqr_status build_plan(int op, int64_t m, int64_t n, int in_dtype, const tsqr_op
         }
         lv.panels = ceil_div(rows, lv.b);
         const size_t es = elem_size(lv.dtype);
-        if (need_q) lv.q1 = take(es * (size_t)rows * n);
+        if (need_q && !(L == 0 && pl.reuse_output)) lv.q1 = take(es * (size_t)rows * n);
         // register panels with n <= 64 keep V and K (Q1 = [I; 0] - V K) instead of forming Q1
         if (need_q && lv.reg && n <= 64) lv.kv = take(es * (size_t)lv.panels * n * n);
         lv.s = take(sizeof(double) * (size_t)lv.panels * n * n);
@@ -187,22 +196,23 @@ inline char *wsp(void *ws, size_t off) { return off ? (char *)ws + off : nullptr
 
 
 // Steps 1-2 (+ finalize): every level's factor launch, then the top.
+// q1_out: the output buffer that holds level 0's panel factors when pl.reuse_output.
 tsqr_status run_factor_levels(const Plan &pl, const void *A, int64_t lda, void *ws,
-                              hipStream_t st)
+                              hipStream_t st, void *q1_out = nullptr)
 {
     for (int L = 0; L < pl.nlev; ++L) {
         const Level &lv = pl.lev[L];
+        void *q1 = (L == 0 && pl.reuse_output) ? q1_out : (void *)wsp(ws, lv.q1);
         const void *X = (L == 0) ? A : (const void *)wsp(ws, pl.lev[L - 1].s);
         const int64_t ldx = (L == 0) ? lda : pl.n;
         const int in_dt = (L == 0) ? pl.in_dtype : F64;
         ProfScope ps(L == 0 ? PC_FACTOR0 : PC_FACTOR_TREE, st);
         if (lv.reg)
-            TSQR_HIP_CHECK(launch_factor_reg(in_dt, lv.dtype, lv.rows, pl.n, X, ldx,
-                                             wsp(ws, lv.q1), (double *)wsp(ws, lv.s),
-                                             wsp(ws, lv.kv), st));
+            TSQR_HIP_CHECK(launch_factor_reg(in_dt, lv.dtype, lv.rows, pl.n, X, ldx, q1,
+                                             (double *)wsp(ws, lv.s), wsp(ws, lv.kv), st));
         else
-            TSQR_HIP_CHECK(launch_factor(in_dt, lv.dtype, lv.rows, pl.n, lv.b, X, ldx,
-                                         wsp(ws, lv.q1), (double *)wsp(ws, lv.s),
+            TSQR_HIP_CHECK(launch_factor(in_dt, lv.dtype, lv.rows, pl.n, lv.b, X, ldx, q1,
+                                         (double *)wsp(ws, lv.s),
                                          lv.global ? wsp(ws, lv.gpanel) : nullptr, st));
     }
     return TSQR_OK;
@@ -210,7 +220,8 @@ tsqr_status run_factor_levels(const Plan &pl, const void *A, int64_t lda, void *
 
 // Step 3 down the tree.  Level 0 writes columns [0, k0) to out0 and [k0, k) to out1.
 tsqr_status run_apply_levels(const Plan &pl, void *ws, int out_dtype, void *out0, int64_t ld0,
-                             int k0, void *out1, int64_t ld1, hipStream_t st)
+                             int k0, void *out1, int64_t ld1, hipStream_t st,
+                             void *q1_out = nullptr)
 {
     const double *W = (const double *)wsp(ws, pl.wtop);
     int64_t ldw = pl.k, wstride = 0;
@@ -226,9 +237,10 @@ tsqr_status run_apply_levels(const Plan &pl, void *ws, int out_dtype, void *out0
             ldw = pl.k;
             wstride = pl.n;
         } else {
-            TSQR_HIP_CHECK(launch_apply_mfma(lv.dtype, out_dtype, lv.rows, pl.n, lv.b,
-                                             wsp(ws, lv.q1), W, ldw, wstride, pl.k, out0, ld0,
-                                             k0, out1, ld1, wsp(ws, lv.kv), st));
+            const void *q1 = pl.reuse_output ? q1_out : (const void *)wsp(ws, lv.q1);
+            TSQR_HIP_CHECK(launch_apply_mfma(lv.dtype, out_dtype, lv.rows, pl.n, lv.b, q1, W, ldw,
+                                             wstride, pl.k, out0, ld0, k0, out1, ld1,
+                                             wsp(ws, lv.kv), st, pl.reuse_output ? 1 : 0));
         }
     }
     return TSQR_OK;
@@ -298,9 +310,10 @@ tsqr_status do_qr(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda
     Plan pl;
     tsqr_status s = build_plan(OP_QR, m, n, in_dtype, o, true, false, pl);
     if (s != TSQR_OK) return s;
+    if (pl.reuse_output && ldq != n) return TSQR_ERR_INVALID_ARG;
     if ((s = check_ws(pl, ws, ws_bytes)) != TSQR_OK) return s;
     hipStream_t st = (hipStream_t)stream;
-    if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
+    if ((s = run_factor_levels(pl, A, lda, ws, st, Q)) != TSQR_OK) return s;
     const Level &top = pl.lev[pl.nlev - 1];
     if (pl.rhat)   // precision form with refinement
         return run_refined(pl, (const double *)A, lda, (double *)Q, ldq, R, ldr, ws, d_info, st);
@@ -310,7 +323,7 @@ tsqr_status do_qr(int in_dtype, int64_t m, int64_t n, const void *A, int64_t lda
                                        (double *)wsp(ws, pl.wtop), pl.k, 1, 0, nullptr, nullptr,
                                        nullptr, nullptr, 0, nullptr, nullptr, d_info, st));
     }
-    return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, nullptr, 0, st);
+    return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, nullptr, 0, st, Q);
 }
 
 // Thin SVD (Sec. III-B, SVD paragraph): R = U_R S V^T at the top of the tree, U_R carried down
@@ -330,10 +343,13 @@ tsqr_status do_svd(int in_dtype, int64_t m, int64_t n, const void *A, int64_t ld
     const bool want_q = Q != nullptr;
     tsqr_status s = build_plan(OP_SVD, m, n, in_dtype, o, want_q, true, pl);
     if (s != TSQR_OK) return s;
+    // with reuse, level 0's panel factors sit in Q when it is wanted, else in U
+    void *q1_out = want_q ? Q : U;
+    if (pl.reuse_output && (want_q ? ldq : ldu) != n) return TSQR_ERR_INVALID_ARG;
     if ((s = check_ws(pl, ws, ws_bytes)) != TSQR_OK) return s;
     hipStream_t st = (hipStream_t)stream;
     const bool f32 = in_dtype == F32;
-    if ((s = run_factor_levels(pl, A, lda, ws, st)) != TSQR_OK) return s;
+    if ((s = run_factor_levels(pl, A, lda, ws, st, q1_out)) != TSQR_OK) return s;
     if (pl.rhat) {
         // refined: Q (caller's or workspace) and R in FP64, then the SVD of R and U = Q U_R
         double *Qd = want_q ? (double *)Q : (double *)wsp(ws, pl.qtmp);
@@ -365,8 +381,8 @@ tsqr_status do_svd(int in_dtype, int64_t m, int64_t n, const void *A, int64_t ld
                                        (double *)wsp(ws, pl.svd_g), (double *)wsp(ws, pl.svd_v),
                                        d_info, st));
     }
-    if (want_q) return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, U, ldu, st);
-    return run_apply_levels(pl, ws, in_dtype, U, ldu, (int)n, nullptr, 0, st);
+    if (want_q) return run_apply_levels(pl, ws, in_dtype, Q, ldq, (int)n, U, ldu, st, q1_out);
+    return run_apply_levels(pl, ws, in_dtype, U, ldu, (int)n, nullptr, 0, st, q1_out);
 }
 
 // Comparison methods of the stability experiment (Sec. IV): workspace = the R-only plan of
@@ -442,6 +458,12 @@ tsqr_status build_bwd_layout(bool svd, int64_t m, int64_t n, const tsqr_opts *o,
 {
     if (o && o->precision != TSQR_FP64) return TSQR_ERR_UNSUPPORTED;
     if (n > TSQR_NMAX_SMALL) return TSQR_ERR_SHAPE;     // the n x n adjoint work in LDS
+    tsqr_opts fo;                                       // the recomputed forward keeps its Q1
+    if (o) {
+        fo = *o;
+        fo.flags &= ~TSQR_FLAG_REUSE_OUTPUT;
+        o = &fo;
+    }
     tsqr_status s = svd ? build_plan(OP_SVD, m, n, F64, o, false, true, bl.fwd)
                         : build_plan(OP_QR, m, n, F64, o, true, false, bl.fwd);
     if (s != TSQR_OK) return s;
@@ -539,16 +561,24 @@ tsqr_status tsqr_workspace_bytes(int32_t op, int64_t m, int64_t n, const tsqr_op
     const tsqr_opts *o = opts_or_default(opts, tmp);
     Plan pl;
     tsqr_status s;
+    // input element type: FP64, except that the reuse flag under TSQR_FP32 implies FP32 input
+    // (the only input whose level-0 factors have the output's element size)
+    const int in_dt = (o->precision == TSQR_FP32 && (o->flags & TSQR_FLAG_REUSE_OUTPUT)) ? F32 : F64;
     switch (op) {
-    case TSQR_OP_R: s = build_plan(OP_R, m, n, F64, o, false, false, pl); break;
-    case TSQR_OP_QR: s = build_plan(OP_QR, m, n, F64, o, true, false, pl); break;
+    case TSQR_OP_R: s = build_plan(OP_R, m, n, in_dt, o, false, false, pl); break;
+    case TSQR_OP_QR: s = build_plan(OP_QR, m, n, in_dt, o, true, false, pl); break;
     case TSQR_OP_SVD: {
-        // the larger of the layouts with and without a Q output
+        // the larger of the layouts with and without a Q output (with the reuse flag, of those
+        // it supports)
         Plan p2;
-        s = build_plan(OP_SVD, m, n, F64, o, true, true, pl);
-        if (s == TSQR_OK && build_plan(OP_SVD, m, n, F64, o, false, true, p2) == TSQR_OK &&
-            p2.total > pl.total)
+        s = build_plan(OP_SVD, m, n, in_dt, o, true, true, pl);
+        const tsqr_status s2 = build_plan(OP_SVD, m, n, in_dt, o, false, true, p2);
+        if (s != TSQR_OK && s2 == TSQR_OK && (o->flags & TSQR_FLAG_REUSE_OUTPUT)) {
+            s = s2;
             pl.total = p2.total;
+        } else if (s == TSQR_OK && s2 == TSQR_OK && p2.total > pl.total) {
+            pl.total = p2.total;
+        }
         break;
     }
     case TSQR_OP_QR_BACKWARD:

@@ -55,11 +55,13 @@ hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t
     return hipGetLastError();
 }
 
+constexpr size_t kMaxLds = 160 * 1024;
+
 template <typename T, typename To>
 hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t ldq,
                         const double *W, int64_t ldw, int64_t wstride, int k, void *out0,
                         int64_t ld0, int k0, void *out1, int64_t ld1, int acc, const void *kmat,
-                        hipStream_t st)
+                        hipStream_t st, int one_slice)
 {
     // Column slices per panel: as few as keep a work-group within 8 output tiles and 80 KB of
     // LDS (the W image plus the staged Q1 blocks), so that two work-groups share a CU.  Every
@@ -67,8 +69,14 @@ hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t 
     const int tiles = (int)ceil_div(k, 16);
     int ny = 1;
     auto nt_of = [&](int y) { return (int)ceil_div(tiles, y); };
-    while (ny < tiles && (nt_of(ny) > 8 || apply_lds_bytes_nt(sizeof(T), n, nt_of(ny)) > 80 * 1024))
-        ++ny;
+    if (one_slice) {
+        if (nt_of(1) > 8 || apply_lds_bytes_nt(sizeof(T), n, nt_of(1)) > kMaxLds)
+            return hipErrorInvalidValue;
+    } else {
+        while (ny < tiles &&
+               (nt_of(ny) > 8 || apply_lds_bytes_nt(sizeof(T), n, nt_of(ny)) > 80 * 1024))
+            ++ny;
+    }
 #define TSQR_NT(NT)                                                                           \
     case NT:                                                                                  \
         return apply_mfma_nt<T, To, NT>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, \
@@ -92,12 +100,13 @@ hipError_t apply_mfma_t(int64_t rows, int64_t n, int b, const void *q1, int64_t 
 hipError_t launch_apply_vk(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                           const void *q1, int64_t ldq, const double *W, int64_t ldw,
                           int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
-                          int64_t ld1, int accumulate, const void *kmat, hipStream_t st)
+                          int64_t ld1, int accumulate, const void *kmat, hipStream_t st,
+                          int one_slice = 0)
 {
     if (n > 4 * kMaxKC) {
         // wide n: the product runs in K chunks of 4 kMaxKC columns of Q1 (rows of W), the
         // first overwriting the output and the others adding to it
-        if (kmat || n > kNmaxWide) return hipErrorInvalidValue;
+        if (kmat || one_slice || n > kNmaxWide) return hipErrorInvalidValue;
         const size_t es = (q_dtype == F64) ? sizeof(double) : sizeof(float);
         for (int64_t c0 = 0; c0 < n; c0 += 4 * kMaxKC) {
             const int64_t nc = std::min<int64_t>(4 * kMaxKC, n - c0);
@@ -113,15 +122,15 @@ hipError_t launch_apply_vk(int q_dtype, int out_dtype, int64_t rows, int64_t n, 
     if (q_dtype == F64) {
         if (out_dtype == F64)
             return apply_mfma_t<double, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0,
-                                                k0, out1, ld1, accumulate, kmat, st);
+                                                k0, out1, ld1, accumulate, kmat, st, one_slice);
         return apply_mfma_t<double, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
-                                           out1, ld1, accumulate, kmat, st);
+                                           out1, ld1, accumulate, kmat, st, one_slice);
     }
     if (out_dtype == F64)
         return apply_mfma_t<float, double>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0,
-                                           out1, ld1, accumulate, kmat, st);
+                                           out1, ld1, accumulate, kmat, st, one_slice);
     return apply_mfma_t<float, float>(rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0, k0, out1,
-                                      ld1, accumulate, kmat, st);
+                                      ld1, accumulate, kmat, st, one_slice);
 }
 
 hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
@@ -136,10 +145,19 @@ hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n,
 hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                              const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
                              void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
-                             const void *kmat, hipStream_t st)
+                             const void *kmat, hipStream_t st, int one_slice)
 {
     return launch_apply_vk(q_dtype, out_dtype, rows, n, b, q1, n, W, ldw, wstride, k, out0, ld0, k0,
-                           out1, ld1, 0, kmat, st);
+                           out1, ld1, 0, kmat, st, one_slice);
+}
+
+bool apply_one_slice_ok(int q_dtype, int out_dtype, int64_t n, int k)
+{
+    (void)out_dtype;
+    if (n < 1 || n > 4 * kMaxKC || k < 1) return false;
+    const int64_t tiles = ceil_div(k, 16);
+    const size_t es = (q_dtype == F64) ? sizeof(double) : sizeof(float);
+    return tiles <= 8 && apply_lds_bytes_nt(es, n, (int)tiles) <= kMaxLds;
 }
 
 }  // namespace tsqr

@@ -82,6 +82,7 @@ struct Plan {
     size_t qtmp = 0;      // m x n FP64 Q for an SVD of the precision form without a Q output
     size_t rhat = 0;      // n x n FP64 R-hat of the FP32 path (precision form with refinement)
     size_t rref = 0;      // n x n FP64 refined R (SVD of the precision form)
+    bool reuse_output = false;   // level-0 panel factors kept in the Q (or U) output
     size_t total = 0;
 };
 
@@ -111,10 +112,15 @@ hipError_t launch_factor_reg(int in_dtype, int dtype, int64_t rows, int64_t n, c
 // out = Q1 * W per panel: panel p (rows [p b, p b + b)) uses W rows [p*wstride, p*wstride + n).
 // Columns [0, k0) of the product go to out0 (ld0), columns [k0, k) to out1 (ld1).  With kmat
 // (n <= 64) q1 holds the reflectors V and kmat the panels' K (Q1 = [I; 0] - V K).
+// one_slice: one work-group covers all k output columns of its rows (no column slices), so the
+// output may be the buffer q1 itself (each row block is read before it is written).
 hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                              const void *q1, const double *W, int64_t ldw, int64_t wstride, int k,
                              void *out0, int64_t ld0, int k0, void *out1, int64_t ld1,
-                             const void *kmat, hipStream_t st);
+                             const void *kmat, hipStream_t st, int one_slice = 0);
+// Whether launch_apply_mfma supports one_slice for (q_dtype, n, k): n <= 128, k <= 128 and the
+// W image plus the staged blocks within one work-group's LDS.
+bool apply_one_slice_ok(int q_dtype, int out_dtype, int64_t n, int k);
 
 // General tall product on the same kernel: out = X * W (X: rows x n, row stride ldq) panel by
 // panel (panel p of b rows uses W rows [p*wstride, +n)); accumulate != 0 adds to out.

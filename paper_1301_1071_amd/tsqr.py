@@ -34,16 +34,17 @@ def _p(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def workspace_bytes(op: str, m: int, n: int, precision: str = "fp64", panel_rows: int = 0) -> int:
-    o = make_opts(precision, panel_rows)
+def workspace_bytes(op: str, m: int, n: int, precision: str = "fp64", panel_rows: int = 0,
+                    reuse_output: bool = False) -> int:
+    o = make_opts(precision, panel_rows, reuse_output)
     out = ctypes.c_size_t(0)
     check(lib().tsqr_workspace_bytes(_lib.OPS[op], m, n, ctypes.byref(o), ctypes.byref(out)),
           "tsqr_workspace_bytes")
     return int(out.value)
 
 
-def _workspace(op, m, n, precision, panel_rows, device):
-    nbytes = workspace_bytes(op, m, n, precision, panel_rows)
+def _workspace(op, m, n, precision, panel_rows, device, reuse_output=False):
+    nbytes = workspace_bytes(op, m, n, precision, panel_rows, reuse_output)
     return torch.empty(nbytes, dtype=torch.uint8, device=device)
 
 
@@ -78,9 +79,10 @@ def r(A: torch.Tensor, panel_rows: int = 0, ws: torch.Tensor | None = None,
 
 def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
        ws: torch.Tensor | None = None, out=None, check_info: bool = True,
-       info: torch.Tensor | None = None):
+       info: torch.Tensor | None = None, reuse_output: bool = False):
     """Thin QR by direct TSQR: returns (Q, R).  precision in {"fp64", "fp32", "fp32_refined"}
-    for FP64 input; FP32 input always runs the FP32 path."""
+    for FP64 input; FP32 input always runs the FP32 path.  reuse_output keeps the level-0 panel
+    factors in Q instead of the workspace (m x n elements less; Q must be contiguous)."""
     _require_gpu_matrix(A, (torch.float64, torch.float32))
     m, n = A.shape
     f32 = A.dtype == torch.float32
@@ -92,9 +94,9 @@ def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
     prec = "fp32" if f32 else precision
-    o = make_opts(prec, panel_rows)
+    o = make_opts(prec, panel_rows, reuse_output)
     if ws is None:
-        ws = _workspace("qr", m, n, prec, panel_rows, A.device)
+        ws = _workspace("qr", m, n, prec, panel_rows, A.device, reuse_output)
     fn = lib().tsqr_qr_f32 if f32 else lib().tsqr_qr
     check(fn(m, n, _p(A), A.stride(0), _p(Q), Q.stride(0), _p(R), R.stride(0), _p(ws), ws.numel(),
              _p(info), ctypes.byref(o), _stream(A.device)), fn.__name__)
@@ -104,10 +106,10 @@ def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
 
 def svd(A: torch.Tensor, want_qr: bool = False, precision: str = "fp64", panel_rows: int = 0,
         ws: torch.Tensor | None = None, out=None, check_info: bool = True,
-        info: torch.Tensor | None = None):
+        info: torch.Tensor | None = None, reuse_output: bool = False):
     """Thin SVD by direct TSQR: returns (U, S, V) or (U, S, V, Q, R) with want_qr.  precision in
     {"fp64", "fp32", "fp32_refined"} for FP64 input; FP32 input runs the FP32 path and returns
-    FP32 results."""
+    FP32 results.  reuse_output keeps the level-0 panel factors in Q (U without want_qr)."""
     _require_gpu_matrix(A, (torch.float64, torch.float32))
     m, n = A.shape
     f32 = A.dtype == torch.float32
@@ -122,9 +124,9 @@ def svd(A: torch.Tensor, want_qr: bool = False, precision: str = "fp64", panel_r
     if info is None:
         info = torch.zeros(1, dtype=torch.int32, device=A.device)
     prec = "fp32" if f32 else precision
-    o = make_opts(prec, panel_rows)
+    o = make_opts(prec, panel_rows, reuse_output)
     if ws is None:
-        ws = _workspace("svd", m, n, prec, panel_rows, A.device)
+        ws = _workspace("svd", m, n, prec, panel_rows, A.device, reuse_output)
     fn = lib().tsqr_svd_f32 if f32 else lib().tsqr_svd
     check(fn(m, n, _p(A), A.stride(0), _p(U), U.stride(0), _p(S), _p(V), V.stride(0),
              _p(Q), Q.stride(0) if Q is not None else 0, _p(R),

@@ -75,7 +75,7 @@ def test_opts_validation():
     assert _ws("qr", 1000, 10, o)[0] == 1
     o = make_opts("fp64"); o.precision = 7
     assert _ws("qr", 1000, 10, o)[0] == 1
-    o = make_opts("fp64"); o.flags = 1
+    o = make_opts("fp64"); o.flags = 4            # not a defined flag
     assert _ws("qr", 1000, 10, o)[0] == 1
     o = make_opts("fp64", panel_rows=5)          # shorter than n
     assert _ws("qr", 1000, 10, o)[0] == 1
@@ -276,3 +276,29 @@ def test_wide_plan_quarters_each_level(n):
         assert st == 0 and nbytes > 0
     assert _ws("qr", m, n, make_opts("fp32_refined"))[0] == 4
     assert _ws("svd_backward", m, n)[0] == 2
+
+
+def test_reuse_output_workspace_and_limits():
+    """TSQR_FLAG_REUSE_OUTPUT drops the m x n level-0 factor buffer from the workspace where one
+    work-group can cover all output columns; elsewhere the query returns TSQR_ERR_UNSUPPORTED."""
+    def ws(op, m, n, prec="fp64", reuse=True):
+        o = make_opts(prec, 0, reuse)
+        out = ctypes.c_size_t(0)
+        st = lib().tsqr_workspace_bytes(_lib.OPS[op], m, n, ctypes.byref(o), ctypes.byref(out))
+        return st, out.value
+    for m, n in [(600_000_000, 25), (4_000_000, 50), (100_000, 10), (20_000, 100)]:
+        st0, b0 = ws("qr", m, n, reuse=False)
+        st1, b1 = ws("qr", m, n)
+        assert st0 == 0 and st1 == 0 and b0 - b1 >= 8 * m * n
+    # A, Q and the workspace of the paper's 600M x 25 QR within 288 GB of HBM
+    assert 2 * 8 * 600_000_000 * 25 + ws("qr", 600_000_000, 25)[1] < 288e9 - 4e9
+    assert ws("qr", 20_000, 128)[0] == 4          # W image of 128 columns past one LDS
+    assert ws("qr", 20_000, 256)[0] == 4          # the wide path runs in column chunks
+    assert ws("qr", 20_000, 25, "fp32")[0] == 0   # FP32 input
+    st, b = ws("svd", 20_000, 100)                # only U: the layout without Q
+    assert st == 0 and b < ws("svd", 20_000, 100, reuse=False)[1]
+    assert ws("r", 20_000, 256)[0] == 0           # ignored without Q
+    assert ws("qr", 20_000, 25, "fp32_refined")[0] == 0
+    o = make_opts("fp64")
+    o.flags = 2
+    assert lib().tsqr_workspace_bytes(1, 1000, 10, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == 1

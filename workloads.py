@@ -13,6 +13,12 @@ scaled to one GPU, with entries drawn as follows (numpy PCG64, fixed seeds):
   mixed-c25  16,000,000 x 25, as svd-c50 with s = logspace(0,-4,25)           seed 1301107103
   batch512   512 matrices, m ~ U{2000..200000}, n ~ U{4,8,16,32,64}, N(0,1)    seed 1301107104
   grad-c100  1,000,000 x 100, N(0,1); cotangents N(0,1) with seed + 100 k      seed 1301107105
+
+Paper-scale shapes (two of the paper's own, Sec. V), built on the device because the inputs
+alone fill much of one GPU's HBM: A = G diag(s) V^T with V and s drawn as above (numpy) and G
+drawn by torch's device generator (Philox) seeded with the same seed, chunk by chunk:
+  paper-600m 600,000,000 x 25,  s = logspace(0,-8,25)                         seed 1301107106
+  paper-150m 150,000,000 x 100, s = logspace(0,-8,100)                        seed 1301107107
 """
 from __future__ import annotations
 
@@ -24,6 +30,13 @@ SEEDS = {
     "mixed-c25": 1301107103,
     "batch512": 1301107104,
     "grad-c100": 1301107105,
+    "paper-600m": 1301107106,
+    "paper-150m": 1301107107,
+}
+
+PAPER_SCALE = {
+    "paper-600m": dict(m=600_000_000, n=25, log_cond=8.0),
+    "paper-150m": dict(m=150_000_000, n=100, log_cond=8.0),
 }
 
 CONFIGS = {
@@ -110,3 +123,23 @@ def batch_matrices(shapes, seed: int = SEEDS["batch512"], dtype=np.float64):
         a = rng(seed + 1 + k).standard_normal((m, n))
         mats.append(a.astype(dtype) if dtype != np.float64 else a)
     return mats
+
+
+def spectrum_matrix_device(out, log_cond: float, seed: int, chunk_rows: int = 1 << 22):
+    """Fill the device tensor `out` (m x n, float64, contiguous) with A = G diag(s) V^T: V Haar
+    and s = logspace(0, -log_cond, n) from numpy as in spectrum_matrix, G ~ N(0,1) from torch's
+    device generator seeded with `seed`, chunk_rows rows at a time.  Returns (s, V)."""
+    import torch
+    m, n = out.shape
+    g = rng(seed)
+    V = haar_orthogonal(n, g)
+    s = np.logspace(0.0, -log_cond, n)
+    B = torch.from_numpy(np.ascontiguousarray(s[:, None] * V.T)).to(out.device)
+    gen = torch.Generator(device=out.device)
+    gen.manual_seed(seed)
+    for r0 in range(0, m, chunk_rows):
+        r1 = min(m, r0 + chunk_rows)
+        G = torch.randn((r1 - r0, n), generator=gen, dtype=torch.float64, device=out.device)
+        torch.matmul(G, B, out=out[r0:r1])
+        del G
+    return s, V
