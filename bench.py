@@ -21,7 +21,8 @@ Prints ONE JSON line:
   forms                 the other workloads on the same GPU: qr-small (graph replays),
                         mixed-c25 (FP64 vs FP32 vs FP32 + refinement), batch512 (FP64 / FP32,
                         per width), grad-c100 (forward vs adjoint), stability (Sec. IV:
-                        ||Q^T Q - I|| of direct TSQR and the comparison methods per condition).
+                        ||Q^T Q - I|| of direct TSQR and the comparison methods per condition),
+                        paper_scale (600M x 25 QR and 150M x 100 R, Sec. V shapes).
 """
 from __future__ import annotations
 
@@ -347,7 +348,8 @@ def main():
 # ----------------------------------------------------------------------------- the other forms
 def bench_forms(args, dev):
     out = {}
-    for fn in (form_qr_small, form_mixed, form_batched, form_grad, form_stability):
+    for fn in (form_qr_small, form_mixed, form_batched, form_grad, form_stability,
+               form_paper_scale):
         t0 = time.perf_counter()
         try:
             out[fn.__name__[5:]] = fn(args, dev)
@@ -543,6 +545,64 @@ def form_stability(args, dev):
                            "backward": tsqr.metric_residual(A, Q, R) / normA, "ms": ms}
         rows["1e%d" % c] = r
     return {"m": m, "n": n, "by_cond": rows}
+
+
+def form_paper_scale(args, dev):
+    """Two of the paper's own shapes (Sec. V) on the one GPU, inputs built on the device:
+    600,000,000 x 25 QR (level-0 factors kept in Q, so that A, Q and the workspace fit in HBM)
+    and 150,000,000 x 100 R only, each the mean of 3 timed calls after one warm-up, with the
+    compensated Sec. I-B metrics.  The paper's Hadoop job times for the same shapes (Tables VI
+    and I, a 40-core cluster reading HDFS) are quoted as context."""
+    import torch
+    import paper_1301_1071_amd as tsqr
+    import workloads
+    res = {}
+    c = workloads.PAPER_SCALE["paper-600m"]
+    m, n = c["m"], c["n"]
+    wsb = tsqr.workspace_bytes("qr", m, n, reuse_output=True)
+    free, _ = torch.cuda.mem_get_info()
+    if free < 16 * m * n + wsb + (2 << 30):
+        res["qr_600m_x_25"] = {"skipped": "%.0f GiB free" % (free / 2 ** 30)}
+    else:
+        A = torch.empty((m, n), dtype=torch.float64, device=dev)
+        workloads.spectrum_matrix_device(A, c["log_cond"], workloads.SEEDS["paper-600m"])
+        Q = torch.empty_like(A)
+        R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        ms = wall_ms(lambda: tsqr.qr(A, ws=ws, out=(Q, R), check_info=False, info=info,
+                                     reuse_output=True), 3, 1)
+        del ws
+        res["qr_600m_x_25"] = {
+            "m": m, "n": n, "ms": ms, "GBps": 16.0 * m * n / (ms * 1e-3) / 1e9,
+            "flops_2mn2_per_s": 2.0 * m * n * n / (ms * 1e-3), "info": int(info.item()),
+            "orth": tsqr.metric_orth(Q),
+            "backward": tsqr.metric_residual(A, Q, R) / float(torch.linalg.matrix_norm(R.cpu(), 2)),
+            "paper_job_s": {"python_table6": 1910, "cxx_table1": 1482}}
+        del A, Q
+        torch.cuda.empty_cache()
+    c = workloads.PAPER_SCALE["paper-150m"]
+    m, n = c["m"], c["n"]
+    wsb = tsqr.workspace_bytes("r", m, n)
+    free, _ = torch.cuda.mem_get_info()
+    if free < 8 * m * n + wsb + (4 << 30):
+        res["r_150m_x_100"] = {"skipped": "%.0f GiB free" % (free / 2 ** 30)}
+    else:
+        A = torch.empty((m, n), dtype=torch.float64, device=dev)
+        workloads.spectrum_matrix_device(A, c["log_cond"], workloads.SEEDS["paper-150m"])
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        ms = wall_ms(lambda: tsqr.r(A, ws=ws, check_info=False), 3, 1)
+        R = tsqr.r(A, ws=ws).cpu().numpy()
+        del ws
+        G = tsqr.metric_gram(2, A).cpu().numpy()
+        res["r_150m_x_100"] = {
+            "m": m, "n": n, "ms": ms, "GBps": 8.0 * m * n / (ms * 1e-3) / 1e9,
+            "gram_err": float(np.max(np.abs(np.linalg.eigvalsh(R.T @ R - G)))
+                              / np.max(np.linalg.eigvalsh(G))),
+            "paper_job_s_qr": {"python_table6": 2154, "cxx_table1": 1503}}
+        del A
+        torch.cuda.empty_cache()
+    return res
 
 
 # ----------------------------------------------------------------------------- CPU baseline
