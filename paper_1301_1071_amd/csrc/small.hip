@@ -61,13 +61,15 @@ __device__ __forceinline__ double group16_sum(double v)
 }
 
 // NPAD: column capacity (128, or 512 for the wide path, whose Jacobi columns are re-read from
-// memory for the rotation instead of being kept in registers)
-template <int NPAD>
+// memory for the rotation instead of being kept in registers).  LDSM: the Jacobi columns live in
+// LDS (known at compile time, so that their accesses are LDS instructions, not flat ones that
+// could reach either memory) or in the global scratch G, Vw.
+template <int NPAD, bool LDSM>
 __global__ void __launch_bounds__(kSvdThreads)
 k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *__restrict__ Rf,
            int64_t ldr, double *__restrict__ Wtop, int k, int want_q, int want_u,
            double *__restrict__ S, float *__restrict__ Sf, double *__restrict__ V,
-           float *__restrict__ Vf, int64_t ldv, double *G, double *Vw, int use_lds,
+           float *__restrict__ Vf, int64_t ldv, double *G, double *Vw,
            int32_t *__restrict__ info, int keep_info)
 {
     extern __shared__ __align__(16) double sm[];
@@ -104,8 +106,8 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
     const int kq = want_q ? n : 0;
 
     if (want_u || S != nullptr || Sf != nullptr) {
-        double *gG = use_lds ? sm : G;                     // column-major n x n
-        double *gV = use_lds ? sm + (size_t)n * n : Vw;
+        double *gG = LDSM ? sm : G;                        // column-major n x n
+        double *gV = LDSM ? sm + (size_t)n * n : Vw;
         // one-sided Jacobi on R^T (column r of R^T is row r of R): R^T J = G with orthogonal
         // columns, so R = J diag(|g|) (G diag(|g|)^{-1})^T, i.e. U_R = J and V = G / |g|.
         // Rotating the rows of the triangular R converges in far fewer sweeps than rotating its
@@ -233,7 +235,8 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
     const int use_lds = (svd && need <= (size_t)kSmallLdsLimit) ? 1 : 0;
     const size_t lds = use_lds ? need : 0;
     if (n > kNmaxWide) return hipErrorInvalidValue;
-    auto kern = (n > kNmaxPad) ? k_finalize<kNmaxWide> : k_finalize<kNmaxPad>;
+    auto kern = (n > kNmaxPad) ? k_finalize<kNmaxWide, false>
+                               : (use_lds ? k_finalize<kNmaxPad, true> : k_finalize<kNmaxPad, false>);
     hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
     if (e != hipSuccess) return e;
     // one 16-lane group per column pair of a Jacobi round, whole waves, so that each round's
@@ -241,7 +244,7 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
     const int64_t pairs = (n + (n & 1)) / 2;
     const int threads = (int)std::min<int64_t>(kSvdThreads, std::max<int64_t>(64, (16 * pairs + 63) / 64 * 64));
     hipLaunchKernelGGL(kern, dim3(1), dim3(threads), lds, st, (int)n, Rt, R,
-                       Rf, ldr, Wtop, k, want_q, want_u, S, Sf, V, Vf, ldv, G, Vw, use_lds, info,
+                       Rf, ldr, Wtop, k, want_q, want_u, S, Sf, V, Vf, ldv, G, Vw, info,
                        keep_info);
     return hipGetLastError();
 }
