@@ -60,7 +60,7 @@ __device__ __forceinline__ double group16_sum(double v)
     return dpp_d<0x150>(v);       // row_newbcast:0
 }
 
-// NPAD: column capacity (128, or 512 for the wide path, whose Jacobi columns are re-read from
+// NPAD: column capacity (64, 128, or 512 for the wide path, whose Jacobi columns are re-read from
 // memory for the rotation instead of being kept in registers).  LDSM: the Jacobi columns live in
 // LDS (known at compile time, so that their accesses are LDS instructions, not flat ones that
 // could reach either memory) or in the global scratch G, Vw.
@@ -134,44 +134,82 @@ k_finalize(int n, const double *__restrict__ Rt, double *__restrict__ R, float *
                     const int p = min(a, bq), q = max(a, bq);
                     if (q >= n) continue;
                     double *gp = gG + (int64_t)p * n, *gq = gG + (int64_t)q * n;
+                    double *vp = gV + (int64_t)p * n, *vq = gV + (int64_t)q * n;
                     double xp[kCache ? NJ : 1], xq[kCache ? NJ : 1];
                     double al = 0.0, be = 0.0, ga = 0.0;
+                    if constexpr (kCache) {
+                        // all chunks (NJ = 16-row chunks of the padded width) loaded at once from
+                        // clamped in-bounds rows, so the loads are in flight together
 #pragma unroll
-                    for (int j = 0; j < NJ; ++j) {
-                        if (j >= nj) break;                    // uniform: chunks past n
-                        const int i = gl + 16 * j;
-                        const double a = (i < n) ? gp[i] : 0.0;
-                        const double c = (i < n) ? gq[i] : 0.0;
-                        if constexpr (kCache) { xp[j] = a; xq[j] = c; }
-                        al = fma(a, a, al);
-                        be = fma(c, c, be);
-                        ga = fma(a, c, ga);
+                        for (int j = 0; j < NJ; ++j) {
+                            const int i = gl + 16 * j, ic = min(i, n - 1);
+                            xp[j] = gp[ic];
+                            xq[j] = gq[ic];
+                        }
+#pragma unroll
+                        for (int j = 0; j < NJ; ++j) {
+                            const bool in = gl + 16 * j < n;
+                            xp[j] = in ? xp[j] : 0.0;
+                            xq[j] = in ? xq[j] : 0.0;
+                            al = fma(xp[j], xp[j], al);
+                            be = fma(xq[j], xq[j], be);
+                            ga = fma(xp[j], xq[j], ga);
+                        }
+                    } else {
+                        for (int j = 0; j < nj; ++j) {
+                            const int i = gl + 16 * j;
+                            const double a = (i < n) ? gp[i] : 0.0;
+                            const double c = (i < n) ? gq[i] : 0.0;
+                            al = fma(a, a, al);
+                            be = fma(c, c, be);
+                            ga = fma(a, c, ga);
+                        }
                     }
                     al = group16_sum(al);
                     be = group16_sum(be);
                     ga = group16_sum(ga);
                     if (ga != 0.0 && ga * ga > tol2 * (al * be)) {
+                        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)); |zeta| < 1 / (2 tol) here,
+                        // so 1 + zeta^2 neither overflows nor needs a correctly rounded root
+                        // (cs and sn are formed from the same t, cs^2 + sn^2 = 1 to rounding)
                         const double zeta = 0.5 * (be - al) * rcp_nr(ga);
+                        const double z2 = fma(zeta, zeta, 1.0);
                         const double tt = ((zeta >= 0.0) ? 1.0 : -1.0) *
-                                          rcp_nr(fabs(zeta) + sqrt(fma(zeta, zeta, 1.0)));
+                                          rcp_nr(fabs(zeta) + z2 * rsqrt_nr(z2));
                         const double cs = rsqrt_nr(fma(tt, tt, 1.0));
                         const double sn = cs * tt;
-                        double *vp = gV + (int64_t)p * n, *vq = gV + (int64_t)q * n;
+                        if constexpr (kCache) {
+                            double yp[NJ], yq[NJ];
 #pragma unroll
-                        for (int j = 0; j < NJ; ++j) {
-                            if (j >= nj) break;
-                            const int i = gl + 16 * j;
-                            if (i < n) {
-                                const double a = kCache ? xp[kCache ? j : 0] : gp[i];
-                                const double c = kCache ? xq[kCache ? j : 0] : gq[i];
-                                gp[i] = cs * a - sn * c;
-                                gq[i] = sn * a + cs * c;
-                                const double yp = vp[i], yq = vq[i];
-                                vp[i] = cs * yp - sn * yq;
-                                vq[i] = sn * yp + cs * yq;
+                            for (int j = 0; j < NJ; ++j) {
+                                const int ic = min(gl + 16 * j, n - 1);
+                                yp[j] = vp[ic];
+                                yq[j] = vq[ic];
+                            }
+#pragma unroll
+                            for (int j = 0; j < NJ; ++j) {
+                                const int i = gl + 16 * j;
+                                if (i < n) {
+                                    gp[i] = cs * xp[j] - sn * xq[j];
+                                    gq[i] = sn * xp[j] + cs * xq[j];
+                                    vp[i] = cs * yp[j] - sn * yq[j];
+                                    vq[i] = sn * yp[j] + cs * yq[j];
+                                }
+                            }
+                        } else {
+                            for (int j = 0; j < nj; ++j) {
+                                const int i = gl + 16 * j;
+                                if (i < n) {
+                                    const double a = gp[i], c = gq[i];
+                                    gp[i] = cs * a - sn * c;
+                                    gq[i] = sn * a + cs * c;
+                                    const double y1 = vp[i], y2 = vq[i];
+                                    vp[i] = cs * y1 - sn * y2;
+                                    vq[i] = sn * y1 + cs * y2;
+                                }
                             }
                         }
-                        if (gl == 0) atomicAdd(&s_rot, 1);
+                        if (gl == 0) s_rot = 1;        // every writer stores the same value
                     }
                 }
                 __syncthreads();
@@ -236,7 +274,8 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
     const size_t lds = use_lds ? need : 0;
     if (n > kNmaxWide) return hipErrorInvalidValue;
     auto kern = (n > kNmaxPad) ? k_finalize<kNmaxWide, false>
-                               : (use_lds ? k_finalize<kNmaxPad, true> : k_finalize<kNmaxPad, false>);
+                : (n > 64) ? (use_lds ? k_finalize<kNmaxPad, true> : k_finalize<kNmaxPad, false>)
+                           : (use_lds ? k_finalize<64, true> : k_finalize<64, false>);
     hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
     if (e != hipSuccess) return e;
     // one 16-lane group per column pair of a Jacobi round, whole waves, so that each round's
