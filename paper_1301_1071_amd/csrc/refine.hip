@@ -25,7 +25,7 @@ namespace {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kRefThreads = 256;     // one row per thread and chunk
-constexpr int kRefMaxBlocks = 1024;  // work-groups (and Gram partials) of a pass
+constexpr int kRefMaxBlocks = 512;   // work-groups (and Gram partials) of a pass: two per CU
 
 // Workspace of the pass, for padded width NP (NP = 16, 32 or 64):
 //   tri   3 x NP x NP  R-hat, Rc1, Rc2 (upper triangular), each stored transposed with the
@@ -237,32 +237,31 @@ k_ref_rows(int64_t m, int n, const double *__restrict__ A, int64_t lda,
     }
 }
 
-// G (upper triangle, np-padded) = sum of the work-groups' partials: four threads per entry, each
-// summing every fourth partial, combined in a fixed order (deterministic).
+// G (upper triangle, np-padded) = sum of the work-groups' partials: one wave per entry, lane l
+// summing the partials l, l + 64, ..., the lanes' sums added by a fixed butterfly (deterministic).
+// With skip_flag, nothing is done unless *skip_flag != 0 (the second pass did not run).
 __global__ void __launch_bounds__(256)
-k_ref_gsum(int n, int np, int nblk, const double *__restrict__ part, double *__restrict__ G)
+k_ref_gsum(int n, int np, int nblk, const double *__restrict__ part, double *__restrict__ G,
+           const int *__restrict__ skip_flag)
 {
+    if (skip_flag && *skip_flag == 0) return;
     const int nent = n * (n + 1) / 2;
-    const int e0 = blockIdx.x * 64 + (threadIdx.x >> 2), q = threadIdx.x & 3;
-    int r = 0, c = 0;
-    if (e0 < nent) {
-        int e = e0;
-        while (e >= n - r) { e -= n - r; ++r; }
-        c = r + e;
-    }
+    const int e0 = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (e0 >= nent) return;                        // whole waves
+    int r = 0, e = e0;
+    while (e >= n - r) { e -= n - r; ++r; }
+    const int c = r + e;
     double a0 = 0.0, a1 = 0.0;
-    if (e0 < nent) {
-        int b = q;
-        for (; b + 4 < nblk; b += 8) {
-            a0 += part[(size_t)b * np * np + r * np + c];
-            a1 += part[(size_t)(b + 4) * np * np + r * np + c];
-        }
-        if (b < nblk) a0 += part[(size_t)b * np * np + r * np + c];
+    int b = lane;
+    for (; b + 64 < nblk; b += 128) {
+        a0 += part[(size_t)b * np * np + r * np + c];
+        a1 += part[(size_t)(b + 64) * np * np + r * np + c];
     }
+    if (b < nblk) a0 += part[(size_t)b * np * np + r * np + c];
     double v = a0 + a1;
-    v += __shfl_xor(v, 1, 64);
-    v += __shfl_xor(v, 2, 64);
-    if (e0 < nent && q == 0) G[r * np + c] = v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (lane == 0) G[r * np + c] = v;
 }
 
 // Cholesky G = Rc^T Rc of the upper triangle of G (n x n in an np-padded array, in place in LDS
@@ -432,16 +431,16 @@ hipError_t launch_refine(int64_t m, int64_t n, const double *A, int64_t lda, con
     if ((e = rows_pass(np, true, m, n, A, lda, tri, 1, nullptr, nullptr, part, nullptr, 0, st)) !=
         hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_ref_gsum, dim3((nent + 63) / 64), dim3(256), 0, st, (int)n, np, L.nblk,
-                       part, G);
+    hipLaunchKernelGGL(k_ref_gsum, dim3((nent + 3) / 4), dim3(256), 0, st, (int)n, np, L.nblk,
+                       part, G, nullptr);
     hipLaunchKernelGGL(k_ref_chol, dim3(1), dim3(256), lds, st, (int)n, np, 1, G, tri, diag, flag,
                        R, ldr, info);
     // pass 1b (skipped on the device unless flag): Y Rc1^{-1}, G2 -> Rc2; then R
     if ((e = rows_pass(np, true, m, n, A, lda, tri, 2, nullptr, flag, part, nullptr, 0, st)) !=
         hipSuccess)
         return e;
-    hipLaunchKernelGGL(k_ref_gsum, dim3((nent + 63) / 64), dim3(256), 0, st, (int)n, np, L.nblk,
-                       part, G);
+    hipLaunchKernelGGL(k_ref_gsum, dim3((nent + 3) / 4), dim3(256), 0, st, (int)n, np, L.nblk,
+                       part, G, flag);
     hipLaunchKernelGGL(k_ref_chol, dim3(1), dim3(256), lds, st, (int)n, np, 2, G, tri, diag, flag,
                        R, ldr, info);
     if ((e = hipGetLastError()) != hipSuccess) return e;
