@@ -106,3 +106,37 @@ def test_qr_wide_f32():
     assert rel(R, Ro) <= 1e-5
     assert orth(Q) <= 1e-5
     assert backward(A, Q, R) <= 1e-5
+
+
+def test_qr_wide_strided_input_and_output():
+    """lda > n and ldq > n on the wide path: the panels read rows at lda, step 3's column chunks
+    write at ldq, and the padding columns of the caller's buffers stay untouched."""
+    import paper_1301_1071_amd as t
+    m, n = 1900, 200
+    big = gauss(m, 232, 17)
+    Ad = to_gpu(big)[:, :n]
+    Qbig = torch.full((m, 210), 7.0, dtype=torch.float64, device=DEV)
+    Rbig = torch.full((n, 205), 7.0, dtype=torch.float64, device=DEV)
+    Q, R = t.qr(Ad, out=(Qbig[:, :n], Rbig[:, :n]))
+    torch.cuda.synchronize()
+    assert torch.all(Qbig[:, n:] == 7.0) and torch.all(Rbig[:, n:] == 7.0)
+    check_qr(big[:, :n].copy(), Q.cpu().numpy(), R.cpu().numpy())
+
+
+def test_svd_wide_f32():
+    """FP32 input at n = 160: FP32 wide panels, FP64 tree and global-memory Jacobi, FP32 outputs."""
+    import paper_1301_1071_amd as t
+    m, n = 2500, 160
+    A32 = gauss(m, n, 23).astype(np.float32)
+    A = A32.astype(np.float64)
+    U, S, V = (x.cpu().numpy().astype(np.float64) for x in t.svd(to_gpu(A32)))
+    _, So, _ = oracle.tsqr_svd(A, block_rows=1000)
+    assert np.abs(S - So).max() <= 1e-5 * So[0]
+    assert orth(U) <= 1e-5 and orth(V) <= 1e-5
+    assert np.linalg.norm(A - (U * S) @ V.T, 2) / S[0] <= 1e-5
+
+
+def test_wide_rejects_reuse_output():
+    import paper_1301_1071_amd as t
+    with pytest.raises(RuntimeError):
+        t.qr(to_gpu(gauss(1000, 200, 3)), reuse_output=True)
