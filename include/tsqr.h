@@ -227,7 +227,8 @@ typedef enum { TSQR_DTYPE_F64 = 0, TSQR_DTYPE_F32 = 1 } tsqr_dtype;
  * FP64 tree of TSQR_FP32).  opts may be NULL; opts->precision must match dtype (TSQR_FP64 or
  * TSQR_FP32); opts->panel_rows = 0 takes each width's panel height from the tune table
  * (tsqr_tune_set), otherwise it must equal one of the heights tsqr_tune_variants lists for
- * every width in the batch.  The plan belongs to the device current at creation.
+ * every width in the batch; opts->flags must be 0 (TSQR_ERR_INVALID_ARG otherwise).  The plan
+ * belongs to the device current at creation.
  */
 tsqr_status tsqr_batch_plan_create(int32_t batch, const int64_t *m, const int64_t *n,
                                    const int64_t *lda, const int64_t *ldq, const int64_t *ldr,
