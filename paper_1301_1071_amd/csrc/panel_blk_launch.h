@@ -15,7 +15,7 @@ using blkpanel::BlkSmem;
 template <typename T, int NCT> struct BlkShape {
     static constexpr int NW = (NCT <= 2) ? 4 : 8;
     static constexpr int RT = (NCT <= 2) ? 6 : ((NCT <= 4) ? 4 : 2);
-    static constexpr int TC = (NCT <= 2) ? NCT : 2;
+    static constexpr int TC = (NCT <= 2) ? NCT : 4;
     static constexpr int B = NW * RT * 16;
     static constexpr size_t LDS = sizeof(BlkSmem<T, NCT, RT, NW, TC>);
     // with the STORE_VK tail (n <= 64)
