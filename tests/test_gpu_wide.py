@@ -140,3 +140,16 @@ def test_wide_rejects_reuse_output():
     import paper_1301_1071_amd as t
     with pytest.raises(RuntimeError):
         t.qr(to_gpu(gauss(1000, 200, 3)), reuse_output=True)
+
+
+def test_wide_info_rank_deficient_and_nonfinite():
+    """d_info on the wide path: a zero column gives R[j][j] == 0 (info j + 1), a NaN gives -1."""
+    import paper_1301_1071_amd as t
+    A = gauss(1500, 200, 4)
+    A[:, 150] = 0.0
+    with pytest.raises(torch.linalg.LinAlgError, match="R\\[150\\]\\[150\\]"):
+        t.qr(to_gpu(A))
+    A = gauss(1500, 200, 4)
+    A[777, 33] = np.nan
+    with pytest.raises(torch.linalg.LinAlgError, match="non-finite"):
+        t.qr(to_gpu(A))
