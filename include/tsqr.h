@@ -106,7 +106,7 @@ tsqr_status tsqr_workspace_bytes(int32_t op, int64_t m, int64_t n, const tsqr_op
 
 /*
  * R factor only (steps 1-2 of Sec. III-B; the indirect TSQR of Sec. II-B computes the same R,
- * "any reduction tree computes R correctly").  A: m x n (lda); R: n x n (ldr), diag(R) > 0.
+ * whatever the shape of the reduction tree).  A: m x n (lda); R: n x n (ldr), diag(R) > 0.
  */
 tsqr_status tsqr_r(int64_t m, int64_t n, const double *A, int64_t lda, double *R, int64_t ldr,
                    void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,

@@ -255,8 +255,8 @@ fail:
 }
 
 /*
- * SVD of a small n x n matrix R (Sec. III-B: "we also compute R = U Sigma V^T"; the paper does not
- * name the method).  One-sided Jacobi (Hestenes; Demmel & Veselic 1992): columns p < q of
+ * SVD of a small n x n matrix R (Sec. III-B: the second step of the SVD variant adds the SVD of the
+ * n x n R; the paper does not name the method).  One-sided Jacobi (Hestenes; Demmel & Veselic 1992): columns p < q of
  * G = R V are rotated until every pair is orthogonal to |g_p^T g_q| <= tol sqrt(|g_p|^2 |g_q|^2),
  * tol = 1e-15 n, in cyclic row order, at most 60 sweeps.  Then s_k = ||g_k||, u_k = g_k / s_k
  * (u_k = 0 when s_k = 0), sorted by descending s.  Gauge: each pair (u_k, v_k) is flipped so that

@@ -3,9 +3,9 @@
 // Sec. III-B: the single reduce task ends with R~; the factorization with a positive diagonal is
 // unique for full-rank A (Sec. I), so R = D R~ with D = diag(sign(R~_jj)), sign(0) = +1, and the
 // step-3 blocks become Q2_p D.  For the SVD variant the reduce task also computes R = U_R S V^T
-// ("computing its SVD is cheap" -- the method is not named): one-sided Jacobi (Hestenes) on R^T,
-// columns rotated until pairwise orthogonal, in parallel round-robin order.  U_R is passed down the tree
-// so that U = Q U_R comes out of step 3 in the same pass as Q.
+// (the paper treats this n x n SVD as negligible and names no method): one-sided Jacobi
+// (Hestenes) on R^T, columns rotated until pairwise orthogonal, in parallel round-robin order.
+// U_R is passed down the tree so that U = Q U_R comes out of step 3 in the same pass as Q.
 #include "tsqr_internal.h"
 
 namespace tsqr {

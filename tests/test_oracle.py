@@ -5,7 +5,7 @@
   factor of an exactly accumulated A^T A, which equals R by Sec. II-A's derivation);
 * closed forms (n = 1, orthonormal A, A = [R0; 0]); a library special case (one block = LAPACK QR
   after the sign fix); invariances (scaling, column scaling, row permutation, block size / tree
-  shape, Sec. II-B "any reduction tree computes R correctly");
+  shape: Sec. II-B notes that the reduction tree does not change R);
 * the paper's stability claim for direct TSQR (Sec. IV: ||Q^T Q - I|| around 1e-15 at every
   condition number tested) and its success metrics (Sec. I-B);
 * central finite differences for the adjoints.
@@ -164,7 +164,7 @@ def test_invariances():
 
 @pytest.mark.parametrize("blocks", [(9, 40, 400), (10, 64, 1000)])
 def test_block_size_and_tree_invariance(blocks):
-    """Sec. II-B: any reduction tree gives the same R (and, with the sign fix, the same Q)."""
+    """Sec. II-B: the shape of the reduction tree does not change R (and, with the sign fix, Q)."""
     A = np.random.default_rng(13).standard_normal((1000, 9))
     ref_q, ref_r = oracle.tsqr(A, block_rows=blocks[0])
     for br in blocks[1:]:
