@@ -156,6 +156,25 @@ tsqr_status tsqr_svd(int64_t m, int64_t n, const double *A, int64_t lda, double 
                      int64_t ldr, void *ws, size_t ws_bytes, int32_t *d_info,
                      const tsqr_opts *opts, void *stream);
 
+/*
+ * Row-chunked thin QR, for inputs whose tsqr_qr workspace would not fit beside A and Q (the
+ * paper's 150,000,000 x 100, Sec. V): one more level of the Sec. III-C recursion above direct
+ * TSQR.  Rows are cut into chunks of chunk_rows (a last chunk shorter than n joins the one
+ * before); each chunk is factored by tsqr_qr with its level-0 factors kept in its rows of Q
+ * (TSQR_FLAG_REUSE_OUTPUT), A_c = Q_c R_c; the stacked R_c are factored by tsqr_qr,
+ * [R_1; ...; R_C] = [Q2_1; ...; Q2_C] R; then Q_c <- Q_c Q2_c in place.  The result is the same
+ * unique factorization (diag(R) > 0) as tsqr_qr's.  FP64 only (opts->precision TSQR_FP64, flags
+ * 0), n <= 128, Q contiguous (ldq == n).  A chunk's own rank deficiency is not reported; d_info
+ * is that of the stacked factorization (the R of A).  Workspace:
+ * tsqr_qr_chunked_workspace_bytes, about one chunk's tsqr_qr workspace.
+ */
+tsqr_status tsqr_qr_chunked_workspace_bytes(int64_t m, int64_t n, int64_t chunk_rows,
+                                            const tsqr_opts *opts, size_t *bytes);
+tsqr_status tsqr_qr_chunked(int64_t m, int64_t n, int64_t chunk_rows, const double *A,
+                            int64_t lda, double *Q, int64_t ldq, double *R, int64_t ldr,
+                            void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
+                            void *stream);
+
 /* FP32 input/output twins: FP32 panels and GEMM, FP64 tree and SVD of R.  opts->precision
  * may be TSQR_FP64 or TSQR_FP32 (both run this path; the workspace query with TSQR_FP32 gives the
  * size); TSQR_FP32_REFINED returns TSQR_ERR_UNSUPPORTED (the refinement needs FP64 input). */

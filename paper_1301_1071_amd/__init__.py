@@ -5,9 +5,9 @@ The factorization runs in hand-written HIP kernels inside ``libtsqr.so`` (C ABI 
 """
 from .tsqr import (BatchPlan, QRFunction, SVDFunction, metric_gram, metric_norm2,  # noqa: F401
                    metric_orth, metric_residual, qr, qr_autograd, qr_backward, qr_batched,
-                   qr_indirect, r, svd, svd_autograd, svd_backward, tune_get, tune_set,
+                   qr_chunked, qr_chunked_workspace_bytes, qr_indirect, r, svd, svd_autograd, svd_backward, tune_get, tune_set,
                    tune_variants, workspace_bytes)
 __all__ = ["qr", "r", "svd", "workspace_bytes", "qr_backward", "svd_backward", "qr_autograd",
            "svd_autograd", "QRFunction", "SVDFunction", "qr_batched", "BatchPlan", "tune_set",
            "tune_get", "tune_variants", "metric_gram", "metric_orth", "metric_norm2",
-           "metric_residual", "qr_indirect"]
+           "metric_residual", "qr_indirect", "qr_chunked", "qr_chunked_workspace_bytes"]

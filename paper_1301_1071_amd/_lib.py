@@ -31,6 +31,9 @@ SIGNATURES = {
     "tsqr_qr": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp, _vp]),
     "tsqr_qr_f32": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp, _vp,
                            _vp]),
+    "tsqr_qr_chunked_workspace_bytes": (_i32, [_i64, _i64, _i64, _vp, ctypes.POINTER(_sz)]),
+    "tsqr_qr_chunked": (_i32, [_i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp, _sz, _vp,
+                               _vp, _vp]),
     "tsqr_svd": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp, _i64,
                         _vp, _sz, _vp, _vp, _vp]),
     "tsqr_svd_f32": (_i32, [_i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64, _vp, _i64, _vp,

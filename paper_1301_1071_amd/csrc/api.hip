@@ -7,6 +7,7 @@
 //   finalize       R = D R~ (+ SVD of R), W_top = [D | D U_R], info;
 //   level T .. 0   apply:   Q1_p * W_p, W_p = rows [p n, p n + n) of the level above (the
 //                  reduce task's k-th key <-> rows (k-1)n+1..kn of its Q, Sec. III-B).
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <stdio.h>
@@ -543,6 +544,72 @@ namespace {
 
 using namespace tsqr;
 
+// Row-chunked QR: one more level of the Sec. III-C recursion above per-chunk direct TSQR.  Chunk
+// c (rows [c h, c h + h), a short last chunk merged into the one before) is factored by tsqr_qr
+// with its level-0 factors kept in its rows of Q, A_c = Q_c R_c; the stacked R_c are factored,
+// [R_1; ...; R_C] = [Q2_1; ...; Q2_C] R; then Q_c <- Q_c Q2_c in place (each row block of Q_c is
+// read before it is written).  Workspace: the stack and Q2 (C n x n each) and the larger of one
+// chunk's and the stack's tsqr_qr workspace, reused by every call in turn.
+namespace {
+
+struct ChunkLayout {
+    int64_t nchunk = 0, h = 0, last = 0;     // chunks, rows per chunk, rows of the last chunk
+    size_t s = 0, q2 = 0, info = 0, inner = 0, inner_bytes = 0, total = 0;
+};
+
+tsqr_opts chunk_inner_opts(const tsqr_opts *o)
+{
+    tsqr_opts r;
+    tsqr_default_opts(&r);
+    if (o) r = *o;
+    r.flags |= TSQR_FLAG_REUSE_OUTPUT;
+    return r;
+}
+
+tsqr_status chunk_layout(int64_t m, int64_t n, int64_t chunk_rows, const tsqr_opts *o,
+                         ChunkLayout &L)
+{
+    if (m <= 0 || n <= 0 || chunk_rows <= 0) return TSQR_ERR_INVALID_ARG;
+    if (m < n || n > TSQR_NMAX) return TSQR_ERR_SHAPE;
+    tsqr_status vs = validate_opts(o, n);
+    if (vs != TSQR_OK) return vs;
+    if (o && (o->precision != TSQR_FP64 || o->flags != 0)) return TSQR_ERR_UNSUPPORTED;
+    L.h = chunk_rows < n ? n : chunk_rows;
+    L.nchunk = ceil_div(m, L.h);
+    L.last = m - (L.nchunk - 1) * L.h;
+    if (L.nchunk > 1 && L.last < n) {        // a last chunk shorter than n joins the one before
+        --L.nchunk;
+        L.last += L.h;
+    }
+    const tsqr_opts io = chunk_inner_opts(o);
+    size_t inner = 0;
+    for (const int64_t rows : {L.h < m ? L.h : m, L.last}) {
+        Plan pc;
+        tsqr_status st = build_plan(OP_QR, rows, n, F64, &io, true, false, pc);
+        if (st != TSQR_OK) return st;
+        inner = std::max(inner, pc.total);
+    }
+    Plan top;
+    tsqr_status st = build_plan(OP_QR, L.nchunk * n, n, F64, o, true, false, top);
+    if (st != TSQR_OK) return st;
+    inner = std::max(inner, top.total);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t at = off;
+        off = align_up(off + (bytes ? bytes : 1));
+        return at;
+    };
+    L.s = take(sizeof(double) * (size_t)L.nchunk * n * n);
+    L.q2 = take(sizeof(double) * (size_t)L.nchunk * n * n);
+    L.info = take(sizeof(int32_t));
+    L.inner = take(inner);
+    L.inner_bytes = inner;
+    L.total = off;
+    return TSQR_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void tsqr_default_opts(tsqr_opts *opts)
@@ -633,6 +700,56 @@ tsqr_status tsqr_qr(int64_t m, int64_t n, const double *A, int64_t lda, double *
                     const tsqr_opts *opts, void *stream)
 {
     return do_qr(F64, m, n, A, lda, Q, ldq, R, nullptr, ldr, ws, ws_bytes, d_info, opts, stream);
+}
+
+
+tsqr_status tsqr_qr_chunked_workspace_bytes(int64_t m, int64_t n, int64_t chunk_rows,
+                                            const tsqr_opts *opts, size_t *bytes)
+{
+    if (!bytes) return TSQR_ERR_INVALID_ARG;
+    ChunkLayout L;
+    tsqr_status s = chunk_layout(m, n, chunk_rows, opts, L);
+    if (s != TSQR_OK) return s;
+    *bytes = L.total;
+    return TSQR_OK;
+}
+
+tsqr_status tsqr_qr_chunked(int64_t m, int64_t n, int64_t chunk_rows, const double *A,
+                            int64_t lda, double *Q, int64_t ldq, double *R, int64_t ldr,
+                            void *ws, size_t ws_bytes, int32_t *d_info, const tsqr_opts *opts,
+                            void *stream)
+{
+    if (!A || !Q || !R || !d_info) return TSQR_ERR_INVALID_ARG;
+    if (lda < n || ldq != n || ldr < n) return TSQR_ERR_INVALID_ARG;
+    ChunkLayout L;
+    tsqr_status s = chunk_layout(m, n, chunk_rows, opts, L);
+    if (s != TSQR_OK) return s;
+    if (!ws || ws_bytes < L.total) return TSQR_ERR_WORKSPACE;
+    hipStream_t st = (hipStream_t)stream;
+    char *base = (char *)ws;
+    double *S = (double *)(base + L.s), *Q2 = (double *)(base + L.q2);
+    int32_t *cinfo = (int32_t *)(base + L.info);
+    void *inner = base + L.inner;
+    const tsqr_opts io = chunk_inner_opts(opts);
+    // a chunk's own rank deficiency is no condition of A (its QR is still exact), so the chunks
+    // report into a scratch flag and only the factorization of the stack writes d_info
+    for (int64_t c = 0; c < L.nchunk; ++c) {
+        const int64_t r0 = c * L.h, rows = (c + 1 < L.nchunk) ? L.h : L.last;
+        s = do_qr(F64, rows, n, A + r0 * lda, lda, Q + r0 * ldq, ldq, S + c * n * n, nullptr, n,
+                  inner, L.inner_bytes, cinfo, &io, stream);
+        if (s != TSQR_OK) return s;
+    }
+    s = do_qr(F64, L.nchunk * n, n, S, n, Q2, n, R, nullptr, ldr, inner, L.inner_bytes, d_info,
+              opts, stream);
+    if (s != TSQR_OK) return s;
+    ProfScope ps(PC_APPLY0, st);
+    for (int64_t c = 0; c < L.nchunk; ++c) {
+        const int64_t r0 = c * L.h, rows = (c + 1 < L.nchunk) ? L.h : L.last;
+        double *Qc = Q + r0 * ldq;
+        TSQR_HIP_CHECK(launch_gemm_mfma(F64, F64, rows, n, 256, Qc, ldq, Q2 + c * n * n, n, 0,
+                                        (int)n, Qc, ldq, (int)n, nullptr, 0, 0, st, 1));
+    }
+    return TSQR_OK;
 }
 
 tsqr_status tsqr_qr_f32(int64_t m, int64_t n, const float *A, int64_t lda, float *Q, int64_t ldq,

@@ -136,10 +136,10 @@ hipError_t launch_apply_vk(int q_dtype, int out_dtype, int64_t rows, int64_t n, 
 hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                             const void *q1, int64_t ldq, const double *W, int64_t ldw,
                             int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
-                            int64_t ld1, int accumulate, hipStream_t st)
+                            int64_t ld1, int accumulate, hipStream_t st, int one_slice)
 {
     return launch_apply_vk(q_dtype, out_dtype, rows, n, b, q1, ldq, W, ldw, wstride, k, out0, ld0,
-                           k0, out1, ld1, accumulate, nullptr, st);
+                           k0, out1, ld1, accumulate, nullptr, st, one_slice);
 }
 
 hipError_t launch_apply_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,

@@ -127,7 +127,7 @@ bool apply_one_slice_ok(int q_dtype, int out_dtype, int64_t n, int k);
 hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n, int b,
                             const void *q1, int64_t ldq, const double *W, int64_t ldw,
                             int64_t wstride, int k, void *out0, int64_t ld0, int k0, void *out1,
-                            int64_t ld1, int accumulate, hipStream_t st);
+                            int64_t ld1, int accumulate, hipStream_t st, int one_slice = 0);
 
 // ---- launchers (backward.hip) ----------------------------------------------------------------
 // Partial Grams C_b = X_b^T Y_b of row blocks (X, Y: m x n FP64) into part (nblk x n x n).

@@ -104,6 +104,38 @@ def qr(A: torch.Tensor, precision: str = "fp64", panel_rows: int = 0,
     return Q, R
 
 
+def qr_chunked_workspace_bytes(m: int, n: int, chunk_rows: int) -> int:
+    out = ctypes.c_size_t(0)
+    o = make_opts("fp64")
+    check(lib().tsqr_qr_chunked_workspace_bytes(m, n, chunk_rows, ctypes.byref(o),
+                                                ctypes.byref(out)), "tsqr_qr_chunked_workspace_bytes")
+    return int(out.value)
+
+
+def qr_chunked(A: torch.Tensor, chunk_rows: int, ws: torch.Tensor | None = None, out=None,
+               check_info: bool = True, info: torch.Tensor | None = None):
+    """Row-chunked thin QR (tsqr_qr_chunked): the same (Q, R) as qr() with a workspace of about
+    one chunk's.  FP64, n <= 128; Q must be contiguous."""
+    _require_gpu_matrix(A, (torch.float64,))
+    m, n = A.shape
+    if out is None:
+        Q = torch.empty((m, n), dtype=A.dtype, device=A.device)
+        R = torch.empty((n, n), dtype=A.dtype, device=A.device)
+    else:
+        Q, R = out
+    if info is None:
+        info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    o = make_opts("fp64")
+    if ws is None:
+        ws = torch.empty(qr_chunked_workspace_bytes(m, n, chunk_rows), dtype=torch.uint8,
+                         device=A.device)
+    check(lib().tsqr_qr_chunked(m, n, chunk_rows, _p(A), A.stride(0), _p(Q), Q.stride(0), _p(R),
+                                R.stride(0), _p(ws), ws.numel(), _p(info), ctypes.byref(o),
+                                _stream(A.device)), "tsqr_qr_chunked")
+    _info_check(info, check_info, "tsqr_qr_chunked")
+    return Q, R
+
+
 def svd(A: torch.Tensor, want_qr: bool = False, precision: str = "fp64", panel_rows: int = 0,
         ws: torch.Tensor | None = None, out=None, check_info: bool = True,
         info: torch.Tensor | None = None, reuse_output: bool = False):

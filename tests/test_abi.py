@@ -302,3 +302,23 @@ def test_reuse_output_workspace_and_limits():
     o = make_opts("fp64")
     o.flags = 2
     assert lib().tsqr_workspace_bytes(1, 1000, 10, ctypes.byref(o), ctypes.byref(ctypes.c_size_t())) == 1
+
+
+def test_chunked_workspace_and_limits():
+    def ws(m, n, h, prec="fp64"):
+        o = make_opts(prec)
+        out = ctypes.c_size_t(0)
+        st = lib().tsqr_qr_chunked_workspace_bytes(m, n, h, ctypes.byref(o), ctypes.byref(out))
+        return st, out.value
+    st, b = ws(150_000_000, 100, 15_000_000)
+    assert st == 0
+    # A, Q and the workspace of the paper's 150M x 100 QR within 288 GB of HBM
+    assert 2 * 8 * 150_000_000 * 100 + b < 288e9 - 10e9
+    st1, b1 = ws(1_000_000, 50, 100_000)
+    st2, b2 = ws(1_000_000, 50, 500_000)
+    assert st1 == 0 and st2 == 0 and b1 < b2                # about one chunk's workspace
+    assert ws(1000, 0, 100)[0] == 1
+    assert ws(1000, 10, 0)[0] == 1
+    assert ws(5, 10, 100)[0] == 2                           # m < n
+    assert ws(100_000, 200, 10_000)[0] == 4                 # the wide path keeps no factors in Q
+    assert ws(100_000, 20, 10_000, "fp32")[0] == 4           # FP64 only

@@ -1,0 +1,45 @@
+"""Row-chunked QR (tsqr_qr_chunked): one more tree level above per-chunk direct TSQR, against the
+oracle element by element (the factorization with diag(R) > 0 is unique, so the chunking does not
+change Q or R beyond rounding)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+DEV = torch.device("cuda:0") if torch.cuda.is_available() else None
+
+
+def gauss(m, n, seed):
+    return np.random.default_rng(seed).standard_normal((m, n))
+
+
+# (m, n, chunk_rows): equal chunks with a ragged last one; a last chunk shorter than n that joins
+# the one before; n = 100 (explicit Q1 panels); one chunk; chunks shorter than a panel
+@pytest.mark.parametrize("m,n,chunk", [(20_000, 30, 6000), (20_010, 30, 5000), (9000, 100, 4000),
+                                       (7000, 50, 10_000), (5000, 8, 300)])
+def test_qr_chunked_vs_oracle(m, n, chunk):
+    import paper_1301_1071_amd as t
+    print(f"chunked m={m} n={n} chunk={chunk}", flush=True)
+    A = gauss(m, n, m + n)
+    Q, R = t.qr_chunked(torch.from_numpy(A).to(DEV), chunk)
+    Q, R = Q.cpu().numpy(), R.cpu().numpy()
+    Qo, Ro = oracle.tsqr(A, block_rows=1000)
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    assert np.linalg.norm(R - Ro) / np.linalg.norm(Ro) <= 1e-12
+    assert np.abs(Q - Qo).max() <= 1e-12
+    assert oracle.metric_orth(Q) <= 1e-12
+    assert oracle.metric_backward(A, Q, R) <= 1e-12
+
+
+def test_qr_chunked_rejections():
+    import paper_1301_1071_amd as t
+    A = torch.from_numpy(gauss(3000, 20, 1)).to(DEV)
+    Qbig = torch.empty((3000, 24), dtype=torch.float64, device=DEV)
+    R = torch.empty((20, 20), dtype=torch.float64, device=DEV)
+    with pytest.raises(RuntimeError):                      # ldq != n
+        t.qr_chunked(A, 1000, out=(Qbig[:, :20], R))
+    with pytest.raises(RuntimeError):                      # wide n: no in-place level 0
+        t.qr_chunked(torch.from_numpy(gauss(2000, 200, 2)).to(DEV), 1000)

@@ -82,3 +82,33 @@ def test_r_150m_x_100():
     assert err <= 1e-12
     del A
     torch.cuda.empty_cache()
+
+
+def test_qr_150m_x_100_chunked():
+    """The paper's widest shape as a full QR: tsqr_qr_chunked with 15,000,000-row chunks keeps the
+    workspace at about one chunk's, so A, Q and the workspace fit in HBM."""
+    import paper_1301_1071_amd as t
+    c = workloads.PAPER_SCALE["paper-150m"]
+    m, n, h = c["m"], c["n"], 15_000_000
+    wsb = t.qr_chunked_workspace_bytes(m, n, h)
+    _need_or_skip(2 * 8 * m * n + wsb + (2 << 30))
+    print("paper-150m qr: generating", flush=True)
+    A = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    workloads.spectrum_matrix_device(A, c["log_cond"], workloads.SEEDS["paper-150m"])
+    Q = torch.empty_like(A)
+    R = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    print("paper-150m qr: factoring", flush=True)
+    t.qr_chunked(A, h, ws=ws, out=(Q, R))
+    torch.cuda.synchronize()
+    del ws
+    print("paper-150m qr: metrics", flush=True)
+    Rn = R.cpu().numpy()
+    assert np.all(np.diag(Rn) > 0) and np.all(np.tril(Rn, -1) == 0)
+    orth = t.metric_orth(Q)
+    back = t.metric_residual(A, Q, R) / np.linalg.norm(Rn, 2)
+    print("paper-150m qr: orth %.3e backward %.3e" % (orth, back), flush=True)
+    assert orth <= 1e-12
+    assert back <= 1e-12
+    del A, Q
+    torch.cuda.empty_cache()
