@@ -549,9 +549,9 @@ def form_stability(args, dev):
 
 def form_paper_scale(args, dev):
     """Two of the paper's own shapes (Sec. V) on the one GPU, inputs built on the device:
-    600,000,000 x 25 QR (level-0 factors kept in Q, so that A, Q and the workspace fit in HBM)
-    and 150,000,000 x 100 R only, each the mean of 3 timed calls after one warm-up, with the
-    compensated Sec. I-B metrics.  The paper's Hadoop job times for the same shapes (Tables VI
+    600,000,000 x 25 QR (level-0 factors kept in Q, so that A, Q and the workspace fit in HBM),
+    150,000,000 x 100 R, and its full QR by the row-chunked driver, each the mean of 3 timed
+    calls after one warm-up, with the compensated Sec. I-B metrics.  The paper's Hadoop job times for the same shapes (Tables VI
     and I, a 40-core cluster reading HDFS) are quoted as context."""
     import torch
     import paper_1301_1071_amd as tsqr
@@ -601,6 +601,29 @@ def form_paper_scale(args, dev):
                               / np.max(np.linalg.eigvalsh(G))),
             "paper_job_s_qr": {"python_table6": 2154, "cxx_table1": 1503}}
         del A
+        torch.cuda.empty_cache()
+    # the full QR of the same shape, in 15,000,000-row chunks (one more tree level)
+    h = 15_000_000
+    wsb = tsqr.qr_chunked_workspace_bytes(m, n, h)
+    free, _ = torch.cuda.mem_get_info()
+    if free < 16 * m * n + wsb + (2 << 30):
+        res["qr_150m_x_100_chunked"] = {"skipped": "%.0f GiB free" % (free / 2 ** 30)}
+    else:
+        A = torch.empty((m, n), dtype=torch.float64, device=dev)
+        workloads.spectrum_matrix_device(A, c["log_cond"], workloads.SEEDS["paper-150m"])
+        Q = torch.empty_like(A)
+        R = torch.empty((n, n), dtype=torch.float64, device=dev)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        ms = wall_ms(lambda: tsqr.qr_chunked(A, h, ws=ws, out=(Q, R), check_info=False,
+                                             info=info), 3, 1)
+        del ws
+        res["qr_150m_x_100_chunked"] = {
+            "m": m, "n": n, "chunk_rows": h, "ms": ms, "GBps": 16.0 * m * n / (ms * 1e-3) / 1e9,
+            "info": int(info.item()), "orth": tsqr.metric_orth(Q),
+            "backward": tsqr.metric_residual(A, Q, R) / float(torch.linalg.matrix_norm(R.cpu(), 2)),
+            "paper_job_s": {"python_table6": 2154, "cxx_table1": 1503}}
+        del A, Q
         torch.cuda.empty_cache()
     return res
 
