@@ -23,8 +23,10 @@ constexpr int kLdsBudget = 150 * 1024;   // bytes of LDS used by one panel work-
 template <typename T>
 __device__ __forceinline__ T shfl_xor(T v, int mask) { return __shfl_xor(v, mask, 64); }
 
-// NPAD: column capacity of the small per-column LDS arrays (128, or 512 for the wide path)
-template <typename Tin, typename T, int NPAD>
+// NPAD: column capacity of the small per-column LDS arrays (128, or 512 for the wide path).
+// GP: the panel lives in the global scratch gpanel (known at compile time, so that LDS panels
+// are addressed with LDS instructions).
+template <typename Tin, typename T, int NPAD, bool GP>
 __global__ void __launch_bounds__(kThreads)
 k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__restrict__ X,
              int64_t ldx, T *__restrict__ q1, double *__restrict__ S, T *gpanel)
@@ -35,9 +37,13 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
     __shared__ T s_tau[NPAD];
     __shared__ T s_umk[NPAD];                     // alpha - beta
     __shared__ T s_beta[NPAD];                    // R_kk
-    // the panel: n columns of ldp rows (column-major), in LDS or, for panels too tall for LDS,
-    // in a global scratch panel (one per work-group)
-    T *P = gpanel ? gpanel + (size_t)blockIdx.x * n * ldp : reinterpret_cast<T *>(smem_raw);
+    // the panel: in LDS n columns of ldp rows (column-major, odd stride: lanes walking down
+    // different columns hit different banks); for panels too tall or wide for LDS, a global
+    // scratch panel (one per work-group) in row-major order, so that the lanes of a wave, which
+    // own consecutive columns, read consecutive addresses of a row
+    T *P = GP ? gpanel + (size_t)blockIdx.x * n * ldp : reinterpret_cast<T *>(smem_raw);
+    const size_t sr = GP ? (size_t)n : 1, sc = GP ? 1 : (size_t)ldp;
+    auto at = [&](int i, int c) -> T & { return P[(size_t)i * sr + (size_t)c * sc]; };
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -55,7 +61,7 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
 
     for (int64_t e = tid; e < (int64_t)re * n; e += kThreads) {
         const int i = (int)(e / n), c = (int)(e - (int64_t)i * n);
-        P[(size_t)c * ldp + i] = (i < bp) ? (T)X[(prow0 + i) * ldx + c] : T(0);
+        at(i, c) = (i < bp) ? (T)X[(prow0 + i) * ldx + c] : T(0);
     }
     __syncthreads();
 
@@ -64,19 +70,16 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
 
     // ---------------- factorization ------------------------------------------------------
     for (int k = 0; k < n; ++k) {
-        const T *xk = P + (size_t)k * ldp;
         const int i0 = max(r0, k + 1);
         for (int ps = 0; ps < npass; ++ps) {
             const int c = cl + ps * NC;
             T d = T(0);
-            if (c >= k && c < n) {
-                const T *pc = P + (size_t)c * ldp;
-                for (int i = i0 + g; i < r1; i += G) d = fma(xk[i], pc[i], d);
-            }
+            if (c >= k && c < n)
+                for (int i = i0 + g; i < r1; i += G) d = fma(at(i, k), at(i, c), d);
             for (int off = NC; off < 64; off <<= 1) d += shfl_xor(d, off);
             if (g == 0 && c < n) {
                 red[w * NPAD + c] = d;
-                if (w == 0) rowk[c] = P[(size_t)c * ldp + k];
+                if (w == 0) rowk[c] = at(k, c);
             }
         }
         __syncthreads();
@@ -98,9 +101,8 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
                     const T pcs = red[c] + red[NPAD + c] + red[2 * NPAD + c] + red[3 * NPAD + c];
                     const T wc = rowk[c] + inv * pcs;          // v^T A[k:, c]
                     const T coef = tau * wc * inv;
-                    T *pc = P + (size_t)c * ldp;
-                    for (int i = i0 + g; i < r1; i += G) pc[i] = fma(-coef, xk[i], pc[i]);
-                    if (w == 0 && g == 0) pc[k] = rowk[c] - tau * wc;
+                    for (int i = i0 + g; i < r1; i += G) at(i, c) = fma(-coef, at(i, k), at(i, c));
+                    if (w == 0 && g == 0) at(k, c) = rowk[c] - tau * wc;
                 }
             }
         }
@@ -110,7 +112,7 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
     // R_p into the stacked buffer: upper triangle of the top n rows, diagonal = beta
     for (int e = tid; e < n * n; e += kThreads) {
         const int r = e / n, c = e - r * n;
-        const double v = (c > r) ? (double)P[(size_t)c * ldp + r] : ((c == r) ? (double)s_beta[r] : 0.0);
+        const double v = (c > r) ? (double)at(r, c) : ((c == r) ? (double)s_beta[r] : 0.0);
         S[(p * n + r) * n + c] = v;
     }
     if (q1 == nullptr) return;
@@ -120,15 +122,12 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
         const T tau = s_tau[k];
         const T umk = s_umk[k];
         const T inv = (umk != T(0)) ? T(1) / umk : T(0);
-        const T *xk = P + (size_t)k * ldp;
         const int i0 = max(r0, k + 1);
         for (int ps = 0; ps < npass; ++ps) {
             const int c = cl + ps * NC;
             T d = T(0);
-            if (c > k && c < n && tau != T(0)) {
-                const T *pc = P + (size_t)c * ldp;
-                for (int i = i0 + g; i < r1; i += G) d = fma(xk[i], pc[i], d);
-            }
+            if (c > k && c < n && tau != T(0))
+                for (int i = i0 + g; i < r1; i += G) d = fma(at(i, k), at(i, c), d);
             for (int off = NC; off < 64; off <<= 1) d += shfl_xor(d, off);
             if (g == 0 && c < n) red[w * NPAD + c] = d;
         }
@@ -140,24 +139,22 @@ k_factor_lds(int64_t rows, int n, int b, int ldp, int nc_log2, const Tin *__rest
                     // row k of column c is zero here (cleared when column c was formed)
                     const T wc = inv * (red[c] + red[NPAD + c] + red[2 * NPAD + c] + red[3 * NPAD + c]);
                     const T coef = tau * wc * inv;
-                    T *pc = P + (size_t)c * ldp;
-                    for (int i = i0 + g; i < r1; i += G) pc[i] = fma(-coef, xk[i], pc[i]);
-                    if (w == 0 && g == 0) pc[k] = -tau * wc;
+                    for (int i = i0 + g; i < r1; i += G) at(i, c) = fma(-coef, at(i, k), at(i, c));
+                    if (w == 0 && g == 0) at(k, c) = -tau * wc;
                 }
             }
         }
         __syncthreads();
-        T *pk = P + (size_t)k * ldp;
         const T sk = -tau * inv;
         for (int i = tid; i < re; i += kThreads) {
-            const T v = (i > k) ? sk * pk[i] : ((i == k) ? T(1) - tau : T(0));
-            pk[i] = v;
+            const T v = (i > k) ? sk * at(i, k) : ((i == k) ? T(1) - tau : T(0));
+            at(i, k) = v;
         }
         __syncthreads();
     }
     for (int64_t e = tid; e < (int64_t)bp * n; e += kThreads) {
         const int i = (int)(e / n), c = (int)(e - (int64_t)i * n);
-        q1[(prow0 + i) * n + c] = P[(size_t)c * ldp + i];
+        q1[(prow0 + i) * n + c] = at(i, c);
     }
 }
 
@@ -177,7 +174,8 @@ hipError_t factor_impl(int64_t rows, int64_t n, int b, const void *X, int64_t ld
 {
     const size_t lds = gpanel ? 0 : lds_bytes<T>((int)n, b);
     if (n > kNmaxWide || (n > kNmaxPad && !gpanel)) return hipErrorInvalidValue;
-    auto kern = (n > kNmaxPad) ? k_factor_lds<Tin, T, kNmaxWide> : k_factor_lds<Tin, T, kNmaxPad>;
+    auto kern = (n > kNmaxPad) ? k_factor_lds<Tin, T, kNmaxWide, true>
+                : gpanel ? k_factor_lds<Tin, T, kNmaxPad, true> : k_factor_lds<Tin, T, kNmaxPad, false>;
     hipError_t e = ensure_dynamic_lds((const void *)kern, lds);
     if (e != hipSuccess) return e;
     const int64_t panels = ceil_div(rows, b);
