@@ -549,8 +549,8 @@ def form_stability(args, dev):
 
 def form_paper_scale(args, dev):
     """Two of the paper's own shapes (Sec. V) on the one GPU, inputs built on the device:
-    600,000,000 x 25 QR (level-0 factors kept in Q, so that A, Q and the workspace fit in HBM),
-    150,000,000 x 100 R, and its full QR by the row-chunked driver, each the mean of 3 timed
+    600,000,000 x 25 QR (level-0 factors kept in Q, so that A, Q and the workspace fit in HBM)
+    and SVD (U in place of Q), 150,000,000 x 100 R, and its full QR by the row-chunked driver, each the mean of 3 timed
     calls after one warm-up, with the compensated Sec. I-B metrics.  The paper's Hadoop job times for the same shapes (Tables VI
     and I, a 40-core cluster reading HDFS) are quoted as context."""
     import torch
@@ -580,6 +580,29 @@ def form_paper_scale(args, dev):
             "backward": tsqr.metric_residual(A, Q, R) / float(torch.linalg.matrix_norm(R.cpu(), 2)),
             "paper_job_s": {"python_table6": 1910, "cxx_table1": 1482}}
         del A, Q
+        torch.cuda.empty_cache()
+    # the SVD variant of the same shape: U out of step 3 in place of Q (level-0 factors in U)
+    wsb = tsqr.workspace_bytes("svd", m, n, reuse_output=True)
+    free, _ = torch.cuda.mem_get_info()
+    if free < 16 * m * n + wsb + (2 << 30):
+        res["svd_600m_x_25"] = {"skipped": "%.0f GiB free" % (free / 2 ** 30)}
+    else:
+        A = torch.empty((m, n), dtype=torch.float64, device=dev)
+        workloads.spectrum_matrix_device(A, c["log_cond"], workloads.SEEDS["paper-600m"])
+        U = torch.empty_like(A)
+        S = torch.empty((n,), dtype=torch.float64, device=dev)
+        V = torch.empty((n, n), dtype=torch.float64, device=dev)
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+        info = torch.zeros(1, dtype=torch.int32, device=dev)
+        ms = wall_ms(lambda: tsqr.svd(A, ws=ws, out=(U, S, V, None, None), check_info=False,
+                                      info=info, reuse_output=True), 3, 1)
+        del ws
+        res["svd_600m_x_25"] = {
+            "m": m, "n": n, "ms": ms, "GBps": 16.0 * m * n / (ms * 1e-3) / 1e9,
+            "info": int(info.item()), "orth_U": tsqr.metric_orth(U),
+            "svd_backward": tsqr.metric_residual(A, U, (S[:, None] * V.t()).contiguous())
+                            / float(S[0])}
+        del A, U
         torch.cuda.empty_cache()
     c = workloads.PAPER_SCALE["paper-150m"]
     m, n = c["m"], c["n"]

@@ -112,3 +112,39 @@ def test_qr_150m_x_100_chunked():
     assert back <= 1e-12
     del A, Q
     torch.cuda.empty_cache()
+
+
+def test_svd_600m_x_25():
+    """The SVD variant (Sec. III-B) at 600,000,000 x 25: U comes out of step 3 in place of Q (its
+    level-0 factors kept in U), S and V from the Jacobi SVD of R.  Checks: ||U^T U - I||_2,
+    ||A - U S V^T||_2 / s_1 and ||V^T V - I||_2 <= 1e-12, S descending and positive, and S against
+    the spectrum A was built from within the O(sqrt(n / m)) distortion of the Gaussian factor."""
+    import paper_1301_1071_amd as t
+    c = workloads.PAPER_SCALE["paper-600m"]
+    m, n = c["m"], c["n"]
+    wsb = t.workspace_bytes("svd", m, n, reuse_output=True)
+    _need_or_skip(2 * 8 * m * n + wsb + (2 << 30))
+    print("paper-600m svd: generating", flush=True)
+    A = torch.empty((m, n), dtype=torch.float64, device="cuda")
+    s_true, _ = workloads.spectrum_matrix_device(A, c["log_cond"], workloads.SEEDS["paper-600m"])
+    U = torch.empty_like(A)
+    S = torch.empty((n,), dtype=torch.float64, device="cuda")
+    V = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    print("paper-600m svd: factoring", flush=True)
+    t.svd(A, ws=ws, out=(U, S, V, None, None), reuse_output=True)
+    torch.cuda.synchronize()
+    del ws
+    print("paper-600m svd: metrics", flush=True)
+    Sn, Vn = S.cpu().numpy(), V.cpu().numpy()
+    assert np.all(Sn > 0) and np.all(np.diff(Sn) <= 0)
+    orth_u = t.metric_orth(U)
+    res = t.metric_residual(A, U, (S[:, None] * V.t()).contiguous()) / Sn[0]
+    orth_v = np.linalg.norm(Vn.T @ Vn - np.eye(n), 2)
+    rel_s = np.max(np.abs(Sn / np.sqrt(m) - s_true) / s_true)
+    print("paper-600m svd: orth U %.3e residual %.3e orth V %.3e |S/sqrt(m) - s|/s %.2e"
+          % (orth_u, res, orth_v, rel_s), flush=True)
+    assert orth_u <= 1e-12 and res <= 1e-12 and orth_v <= 1e-12
+    assert rel_s <= 1e-2
+    del A, U
+    torch.cuda.empty_cache()
