@@ -43,3 +43,35 @@ def test_qr_chunked_rejections():
         t.qr_chunked(A, 1000, out=(Qbig[:, :20], R))
     with pytest.raises(RuntimeError):                      # wide n: no in-place level 0
         t.qr_chunked(torch.from_numpy(gauss(2000, 200, 2)).to(DEV), 1000)
+
+
+def test_qr_chunked_graph_capture_replays():
+    """The chunked driver only enqueues kernels: one call captured in a HIP graph replays to the
+    eager result, several times, with eager work between the replays."""
+    import paper_1301_1071_amd as t
+    m, n, h = 12_000, 24, 5000
+    A = torch.from_numpy(gauss(m, n, 3)).to(DEV)
+    Q = torch.empty((m, n), dtype=torch.float64, device=DEV)
+    R = torch.empty((n, n), dtype=torch.float64, device=DEV)
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    ws = torch.empty(t.qr_chunked_workspace_bytes(m, n, h), dtype=torch.uint8, device=DEV)
+    t.qr_chunked(A, h, ws=ws, out=(Q, R), info=info)
+    torch.cuda.synchronize()
+    Q0, R0 = Q.clone(), R.clone()
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        t.qr_chunked(A, h, ws=ws, out=(Q, R), info=info, check_info=False)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        t.qr_chunked(A, h, ws=ws, out=(Q, R), info=info, check_info=False)
+    for _ in range(3):
+        Q.zero_()
+        R.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(Q, Q0) and torch.equal(R, R0)
+        _ = torch.linalg.norm(A)               # eager work between replays
+        torch.cuda.synchronize()

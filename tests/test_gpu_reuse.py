@@ -59,3 +59,13 @@ def test_reuse_output_rejections():
         t.qr(A, out=(Qbig[:, :20], R), reuse_output=True)
     with pytest.raises(RuntimeError):                      # 128 output columns past one LDS
         t.qr(gauss(2000, 128, 2), reuse_output=True)
+
+
+def test_svd_f32_reuse_output_bitwise():
+    import paper_1301_1071_amd as t
+    A = gauss(30_000, 40, 13, np.float32)
+    a = t.svd(A)
+    b = t.svd(A, reuse_output=True)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
