@@ -11,7 +11,7 @@
 namespace tsqr {
 namespace {
 
-constexpr int kSmallLdsLimit = 150 * 1024;
+constexpr size_t kLdsPerWorkgroup = 160 * 1024;   // LDS one work-group may hold on gfx950
 
 // player at position `pos` of round `r` in the round-robin tournament of np players
 // (0 <= pos < np, 0 <= r < np - 1): player 0 stays, the others rotate by one place per round.
@@ -269,10 +269,20 @@ hipError_t launch_finalize(int64_t n, const double *Rt, double *R, float *Rf, in
                            int32_t *info, hipStream_t st, int keep_info)
 {
     const bool svd = want_u || S != nullptr || Sf != nullptr;
-    const size_t need = svd ? 2 * sizeof(double) * (size_t)n * n : 0;
-    const int use_lds = (svd && need <= (size_t)kSmallLdsLimit) ? 1 : 0;
-    const size_t lds = use_lds ? need : 0;
     if (n > kNmaxWide) return hipErrorInvalidValue;
+    // the Jacobi columns (G and V, 2 n^2 doubles) go to LDS when they fit beside the kernel's
+    // static arrays (up to n = 100 with the 128-column instantiation), else to global scratch
+    const size_t need = svd ? 2 * sizeof(double) * (size_t)n * n : 0;
+    bool use_lds = false;
+    if (svd && n <= kNmaxPad) {
+        const void *lk = (n > 64) ? (const void *)k_finalize<kNmaxPad, true>
+                                  : (const void *)k_finalize<64, true>;
+        hipFuncAttributes fa;
+        hipError_t e = hipFuncGetAttributes(&fa, lk);
+        if (e != hipSuccess) return e;
+        use_lds = need + align_up(fa.sharedSizeBytes, 16) <= kLdsPerWorkgroup;
+    }
+    const size_t lds = use_lds ? need : 0;
     auto kern = (n > kNmaxPad) ? k_finalize<kNmaxWide, false>
                 : (n > 64) ? (use_lds ? k_finalize<kNmaxPad, true> : k_finalize<kNmaxPad, false>)
                            : (use_lds ? k_finalize<64, true> : k_finalize<64, false>);

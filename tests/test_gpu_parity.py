@@ -130,7 +130,10 @@ def check_svd(A, U, S, V, tol_vec=1e-10, block_rows=1000):
         assert np.abs(U - Uo).max() <= tol_vec
 
 
-@pytest.mark.parametrize("m,n", [(20_000, 10), (5000, 50), (3001, 3), (2000, 64), (4000, 100)])
+# n = 100: Jacobi columns in LDS (the largest width whose 2 n^2 doubles fit); n = 120: in
+# global scratch
+@pytest.mark.parametrize("m,n", [(20_000, 10), (5000, 50), (3001, 3), (2000, 64), (4000, 100),
+                                 (3000, 120)])
 def test_svd_fp64(m, n):
     t = tsqr_mod()
     A = gauss(m, n, 40 + n)
