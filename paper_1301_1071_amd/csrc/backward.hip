@@ -114,122 +114,118 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// Rinv = R^{-1} (R upper triangular, n x n, n <= 128): one wave per column j solves R x = e_j by
-// back substitution; lane t keeps x_t and x_{t+64} in registers, so each step is two FMAs, a
-// wave sum and one division, with the next row of R fetched while the current step reduces.
-__device__ void tri_inverse(int n, const double *R, double *Rinv)
+// Row j of R^{-T} (column j of R^{-1}, R upper triangular, n <= 128) into W2[j][:]: one wave
+// per work-group solves R x = e_j by back substitution; lane t keeps x_t and x_{t+64} in
+// registers, so each step is two FMAs, a wave sum and one division, with the next row of R
+// fetched while the current step reduces.  Work-group 0 also flags a zero diagonal (info = -3).
+__global__ void __launch_bounds__(64)
+k_qr_bwd_rinv(int n, const double *__restrict__ R, double *__restrict__ W2,
+              int32_t *__restrict__ info)
 {
-    const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6, nwaves = blockDim.x >> 6;
-    for (int j = wave; j < n; j += nwaves) {
-        double x0 = 0.0, x1 = 0.0;                       // x_lane, x_{lane+64}
-        double r0 = (lane <= j) ? R[j * n + lane] : 0.0;
-        double r1 = (lane + 64 <= j) ? R[j * n + lane + 64] : 0.0;
-        for (int i = j; i >= 0; --i) {
-            // prefetch row i - 1 (columns up to j)
-            double n0 = 0.0, n1 = 0.0;
-            if (i > 0) {
-                n0 = (lane <= j) ? R[(i - 1) * n + lane] : 0.0;
-                n1 = (lane + 64 <= j) ? R[(i - 1) * n + lane + 64] : 0.0;
-            }
-            // sum_{t > i} R[i][t] x_t (x_t = 0 for t > j or not yet computed)
-            double part = 0.0;
-            if (lane > i) part = fma(r0, x0, part);
-            if (lane + 64 > i) part = fma(r1, x1, part);
-            const double s = wave_sum(part);
-            const double rii = __shfl(i < 64 ? r0 : r1, i & 63, 64);
-            const double xi = (((i == j) ? 1.0 : 0.0) - s) / rii;
-            if (lane == i) x0 = xi;
-            if (lane + 64 == i) x1 = xi;
-            r0 = n0;
-            r1 = n1;
+    const int lane = threadIdx.x;
+    const int j = blockIdx.x;
+    double x0 = 0.0, x1 = 0.0;                       // x_lane, x_{lane+64}
+    double r0 = (lane <= j) ? R[j * n + lane] : 0.0;
+    double r1 = (lane + 64 <= j) ? R[j * n + lane + 64] : 0.0;
+    for (int i = j; i >= 0; --i) {
+        // prefetch row i - 1 (columns up to j)
+        double n0 = 0.0, n1 = 0.0;
+        if (i > 0) {
+            n0 = (lane <= j) ? R[(i - 1) * n + lane] : 0.0;
+            n1 = (lane + 64 <= j) ? R[(i - 1) * n + lane + 64] : 0.0;
         }
-        if (lane < n) Rinv[lane * n + j] = (lane <= j) ? x0 : 0.0;
-        if (lane + 64 < n) Rinv[(lane + 64) * n + j] = (lane + 64 <= j) ? x1 : 0.0;
+        // sum_{t > i} R[i][t] x_t (x_t = 0 for t > j or not yet computed)
+        double part = 0.0;
+        if (lane > i) part = fma(r0, x0, part);
+        if (lane + 64 > i) part = fma(r1, x1, part);
+        const double s = wave_sum(part);
+        const double rii = __shfl(i < 64 ? r0 : r1, i & 63, 64);
+        const double xi = (((i == j) ? 1.0 : 0.0) - s) / rii;
+        if (lane == i) x0 = xi;
+        if (lane + 64 == i) x1 = xi;
+        r0 = n0;
+        r1 = n1;
     }
-}
-
-// G = dQ^T Q (NULL: dQ = 0); scratch (2 n^2): Rinv, C
-__global__ void __launch_bounds__(1024)
-k_qr_bwd_small(int n, const double *__restrict__ R, const double *__restrict__ dR, int64_t lddr,
-               const double *__restrict__ G, double *__restrict__ W2,
-               double *__restrict__ scratch, int32_t *__restrict__ info)
-{
-    double *Rinv = scratch, *C = scratch + (size_t)n * n;
-    const int tid = threadIdx.x;
-    tri_inverse(n, R, Rinv);
-    __syncthreads();
-    // M = R triu(dR)^T - G, then C = copyltu(M) (lower triangle mirrored up)
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        if (j > i) continue;
-        double mij = 0.0, mji = 0.0;
-        if (dR) {
-            for (int k = j; k < n; ++k) mij = fma(R[i * n + k], dR[(int64_t)j * lddr + k], mij);
-            (void)mji;
-        }
-        if (G) mij -= G[i * n + j];
-        C[i * n + j] = mij;
-        C[j * n + i] = mij;
-    }
-    __syncthreads();
-    // W2 = [R^{-T}; C R^{-T}]
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        W2[(int64_t)i * n + j] = Rinv[j * n + i];
-        double acc = 0.0;
-        for (int t = j; t < n; ++t) acc = fma(C[i * n + t], Rinv[j * n + t], acc);
-        W2[(int64_t)(n + i) * n + j] = acc;
-    }
-    if (tid == 0) {
+    if (lane < n) W2[(int64_t)j * n + lane] = (lane <= j) ? x0 : 0.0;
+    if (lane + 64 < n) W2[(int64_t)j * n + lane + 64] = (lane + 64 <= j) ? x1 : 0.0;
+    if (j == 0 && lane == 0) {
         int bad = 0;
         for (int i = 0; i < n; ++i) bad |= !(R[i * n + i] != 0.0);
         if (bad) *info = -3;
     }
 }
 
-// UtdU = U^T dU (NULL: dU = 0); scratch (2 n^2): VtdV, T1
-__global__ void __launch_bounds__(1024)
-k_svd_bwd_small(int n, const double *__restrict__ S, const double *__restrict__ V,
-                const double *__restrict__ dS, const double *__restrict__ dV, int64_t lddv,
-                const double *__restrict__ UtdU, double *__restrict__ W2,
-                double *__restrict__ scratch, int32_t *__restrict__ info)
+// Row i of C = copyltu(M), M = R triu(dR)^T - G (lower triangle), into LDS, then row i of the
+// lower block of W2 = C R^{-T}, with R^{-T} from the top block of W2 (lower triangular, read
+// along rows so that the lanes load consecutive entries).  One work-group of 128 threads per
+// row; thread j forms entry j.  G == nullptr: dQ = 0.
+__global__ void __launch_bounds__(128)
+k_qr_bwd_rows(int n, const double *__restrict__ R, const double *__restrict__ dR, int64_t lddr,
+              const double *__restrict__ G, double *__restrict__ W2)
 {
-    double *VtdV = scratch, *T1 = scratch + (size_t)n * n;
-    const int tid = threadIdx.x;
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
-        double acc = 0.0;
-        if (dV)
-            for (int k = 0; k < n; ++k) acc = fma(V[k * n + i], dV[(int64_t)k * lddv + j], acc);
-        VtdV[e] = acc;
+    __shared__ double c_row[128];
+    const int i = blockIdx.x, j = threadIdx.x;
+    if (j < n) {
+        // M[a][b], b <= a: sum_{k >= b} R[a][k] dR[b][k] - G[a][b]
+        const int a = (j <= i) ? i : j, b = (j <= i) ? j : i;
+        double m = 0.0;
+        if (dR)
+            for (int k = b; k < n; ++k) m = fma(R[a * n + k], dR[(int64_t)b * lddr + k], m);
+        if (G) m -= G[a * n + b];
+        c_row[j] = m;
     }
     __syncthreads();
-    // T1 = J S + diag(dS) + S K - (U^T dU) S^{-1}
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
+    if (j < n) {
+        double acc = 0.0;
+        for (int t = j; t < n; ++t) acc = fma(c_row[t], W2[(int64_t)t * n + j], acc);
+        W2[(int64_t)(n + i) * n + j] = acc;
+    }
+}
+
+// Row i of T1 = J S + diag(dS) + S K - (U^T dU) S^{-1} (J, K from U^T dU and V^T dV, whose
+// entries (i, j) and (j, i) thread j forms with the lanes reading consecutive columns), then row
+// i of W2 = [T1 V^T; S^{-1} V^T] with V^T staged in LDS.  One work-group of 128 threads per row.
+// Work-group 0 flags singular values that are not positive and distinct (info = -3).
+__global__ void __launch_bounds__(128)
+k_svd_bwd_rows(int n, const double *__restrict__ S, const double *__restrict__ V,
+               const double *__restrict__ dS, const double *__restrict__ dV, int64_t lddv,
+               const double *__restrict__ UtdU, double *__restrict__ W2,
+               int32_t *__restrict__ info)
+{
+    extern __shared__ double vt[];                   // vt[t * n + j] = V[j][t]
+    __shared__ double t1_row[128];
+    const int i = blockIdx.x, j = threadIdx.x;
+    for (int e = j; e < n * n; e += blockDim.x) {
+        const int r = e / n, c = e - r * n;
+        vt[c * n + r] = V[e];
+    }
+    if (j < n) {
+        double vij = 0.0, vji = 0.0;                 // (V^T dV)[i][j], (V^T dV)[j][i]
+        if (dV)
+            for (int k = 0; k < n; ++k) {
+                vij = fma(V[k * n + i], dV[(int64_t)k * lddv + j], vij);
+                vji = fma(V[k * n + j], dV[(int64_t)k * lddv + i], vji);
+            }
         const double F = (i == j) ? 0.0 : 1.0 / (S[j] * S[j] - S[i] * S[i]);
         const double uij = UtdU ? UtdU[i * n + j] : 0.0, uji = UtdU ? UtdU[j * n + i] : 0.0;
         const double Jij = F * (uij - uji);
-        const double Kij = F * (VtdV[i * n + j] - VtdV[j * n + i]);
+        const double Kij = F * (vij - vji);
         double v = Jij * S[j] + S[i] * Kij - uij / S[j];
         if (i == j && dS) v += dS[i];
-        T1[e] = v;
+        t1_row[j] = v;
     }
     __syncthreads();
-    // W2 = [T1 V^T; S^{-1} V^T]
-    for (int e = tid; e < n * n; e += blockDim.x) {
-        const int i = e / n, j = e - i * n;
+    if (j < n) {
         double acc = 0.0;
-        for (int t = 0; t < n; ++t) acc = fma(T1[i * n + t], V[j * n + t], acc);
+        for (int t = 0; t < n; ++t) acc = fma(t1_row[t], vt[t * n + j], acc);
         W2[(int64_t)i * n + j] = acc;
-        W2[(int64_t)(n + i) * n + j] = V[j * n + i] / S[i];
+        W2[(int64_t)(n + i) * n + j] = vt[i * n + j] / S[i];
     }
-    if (tid == 0) {
+    if (i == 0 && j == 0) {
         int bad = 0;
-        for (int i = 0; i < n; ++i) {
-            bad |= !(S[i] > 0.0);
-            if (i > 0) bad |= !(S[i - 1] != S[i]);
+        for (int k = 0; k < n; ++k) {
+            bad |= !(S[k] > 0.0);
+            if (k > 0) bad |= !(S[k - 1] != S[k]);
         }
         if (bad) *info = -3;
     }
@@ -267,8 +263,11 @@ hipError_t launch_qr_bwd_small(int64_t n, const double *R, const double *dR, int
                                const double *G, double *W2, double *scratch, int32_t *info,
                                hipStream_t st)
 {
-    hipLaunchKernelGGL(k_qr_bwd_small, dim3(1), dim3(1024), 0, st, (int)n, R, dR, lddr, G, W2,
-                       scratch, info);
+    (void)scratch;
+    if (n < 1 || n > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_qr_bwd_rinv, dim3((unsigned)n), dim3(64), 0, st, (int)n, R, W2, info);
+    hipLaunchKernelGGL(k_qr_bwd_rows, dim3((unsigned)n), dim3(128), 0, st, (int)n, R, dR, lddr, G,
+                       W2);
     return hipGetLastError();
 }
 
@@ -276,8 +275,13 @@ hipError_t launch_svd_bwd_small(int64_t n, const double *S, const double *V, con
                                 const double *dV, int64_t lddv, const double *UtdU, double *W2,
                                 double *scratch, int32_t *info, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_svd_bwd_small, dim3(1), dim3(1024), 0, st, (int)n, S, V, dS, dV, lddv,
-                       UtdU, W2, scratch, info);
+    (void)scratch;
+    if (n < 1 || n > 128) return hipErrorInvalidValue;
+    const size_t lds = sizeof(double) * (size_t)n * n;
+    hipError_t e = ensure_dynamic_lds((const void *)k_svd_bwd_rows, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_svd_bwd_rows, dim3((unsigned)n), dim3(128), lds, st, (int)n, S, V, dS, dV,
+                       lddv, UtdU, W2, info);
     return hipGetLastError();
 }
 

@@ -134,6 +134,8 @@ hipError_t launch_gemm_mfma(int q_dtype, int out_dtype, int64_t rows, int64_t n,
 int gram_blocks(int64_t m);
 hipError_t launch_gram(int64_t m, int64_t n, const double *X, int64_t ldx, const double *Y,
                        int64_t ldy, double *part, double *G, hipStream_t st);
+// The n x n middle steps (n <= 128) as row-parallel launches, one work-group per row of W2;
+// `scratch` is not used.
 hipError_t launch_qr_bwd_small(int64_t n, const double *R, const double *dR, int64_t lddr,
                                const double *G, double *W2, double *scratch, int32_t *info,
                                hipStream_t st);
