@@ -34,6 +34,7 @@ k_gram(int64_t m, int n, const double *__restrict__ X, int64_t ldx, const double
     constexpr int T = NP / 16, NTILE = T * T, TPW = (NTILE + 3) / 4;   // tiles per wave
     constexpr int LDS_LD = NP + 1;
     constexpr int PER = kGramRows * NP / kGramThreads;                 // prefetched values
+    static_assert(kGramRows * NP % kGramThreads == 0, "whole prefetch rounds");
     __shared__ double xs[kGramRows * LDS_LD], ys[kGramRows * LDS_LD];
     const int tid = threadIdx.x, lane = tid & 63;
     const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -235,7 +236,8 @@ k_svd_bwd_rows(int n, const double *__restrict__ S, const double *__restrict__ V
 
 int gram_blocks(int64_t m)
 {
-    int64_t b = ceil_div(m, 4096);
+    // about 2,048 rows per work-group: two work-groups per CU at a million rows
+    int64_t b = ceil_div(m, 2048);
     return (int)(b < 1 ? 1 : (b > kGramMaxBlocks ? kGramMaxBlocks : b));
 }
 
@@ -247,11 +249,18 @@ hipError_t launch_gram(int64_t m, int64_t n, const double *X, int64_t ldx, const
 #define TSQR_GRAM(NP)                                                                          \
     hipLaunchKernelGGL(k_gram<NP>, dim3(nb), dim3(kGramThreads), 0, st, m, (int)n, X, ldx, Y,  \
                        ldy, rpb, part)
-    if (n <= 16) TSQR_GRAM(16);
-    else if (n <= 32) TSQR_GRAM(32);
-    else if (n <= 64) TSQR_GRAM(64);
-    else if (n <= 128) TSQR_GRAM(128);
-    else return hipErrorInvalidValue;
+    // the tile grid padded to the next multiple of 16 columns only
+    switch ((n + 15) / 16) {
+    case 1: TSQR_GRAM(16); break;
+    case 2: TSQR_GRAM(32); break;
+    case 3: TSQR_GRAM(48); break;
+    case 4: TSQR_GRAM(64); break;
+    case 5: TSQR_GRAM(80); break;
+    case 6: TSQR_GRAM(96); break;
+    case 7: TSQR_GRAM(112); break;
+    case 8: TSQR_GRAM(128); break;
+    default: return hipErrorInvalidValue;
+    }
 #undef TSQR_GRAM
     const int64_t nn = n * n;
     hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, st, nn, part,
