@@ -96,15 +96,19 @@ k_gram(int64_t m, int n, const double *__restrict__ X, int64_t ldx, const double
     }
 }
 
-// G = sum of the partial Grams, in block order (one thread per entry)
+// G = sum of the partial Grams (one thread per entry), blocks y, y + S, y + 2S, ... of split
+// y = blockIdx.y summed in block order; with S > 1 the sum of split y goes to slot y of part
+// (slot y is read only by split y, first) and a second launch with S = 1 adds the S slots.
 __global__ void __launch_bounds__(256)
-k_gram_sum(int64_t nn, const double *__restrict__ part, int nblk, double *__restrict__ G)
+k_gram_sum(int64_t nn, double *part, int nblk, double *__restrict__ G)
 {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nn) return;
+    const int y = blockIdx.y, S = gridDim.y;
     double a = 0.0;
-    for (int b = 0; b < nblk; ++b) a += part[(int64_t)b * nn + e];
-    G[e] = a;
+    for (int b = y; b < nblk; b += S) a += part[(int64_t)b * nn + e];
+    if (S > 1) part[(int64_t)y * nn + e] = a;
+    else G[e] = a;
 }
 
 // v summed over the 64 lanes of the wave (every lane gets the sum)
@@ -263,8 +267,13 @@ hipError_t launch_gram(int64_t m, int64_t n, const double *X, int64_t ldx, const
     }
 #undef TSQR_GRAM
     const int64_t nn = n * n;
+    // the partials summed in 16 interleaved splits first when there are many of them
+    const int splits = nb >= 64 ? 16 : 1;
+    if (splits > 1)
+        hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ceil_div(nn, 256), splits), dim3(256), 0, st,
+                           nn, part, nb, G);
     hipLaunchKernelGGL(k_gram_sum, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, st, nn, part,
-                       nb, G);
+                       splits > 1 ? splits : nb, G);
     return hipGetLastError();
 }
 
