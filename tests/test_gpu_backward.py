@@ -85,8 +85,10 @@ def test_qr_backward_strided_cotangent_and_output():
 
 
 # --------------------------------------------------------------------- SVD adjoint vs oracle
+# n = 1 and n = 128: the narrowest and widest n x n middle steps (one work-group per row of W2)
 @pytest.mark.parametrize("m,n,log_cond", [(2000, 8, 2.0), (5000, 50, 3.0), (3001, 3, 1.0),
-                                          (20_000, 100, 2.0), (4000, 30, None)])
+                                          (20_000, 100, 2.0), (4000, 30, None), (700, 1, None),
+                                          (3000, 128, 1.0)])
 def test_svd_backward_vs_oracle(m, n, log_cond):
     if log_cond is None:
         A = np.random.default_rng(600 + n).standard_normal((m, n))
