@@ -43,10 +43,11 @@ hipError_t apply_mfma_nt(int64_t rows, int64_t n, int b, const void *q1, int64_t
     if (e != hipSuccess) return e;
     const int64_t panels = ceil_div(rows, b);
     const int ny = (int)ceil_div(k, 16 * NT);
-    // row chunks: enough work-groups to cover the chip (2048), at most one 16-row block per wave
-    // and chunk round
+    // row chunks: about 1024 work-groups (four per CU), at most one 16-row block per wave and
+    // chunk round.  A launch with hundreds of panels (the first tree level of a tall matrix)
+    // then keeps one work-group per panel, which measured faster than splitting its rows
     const int max_chunks = (int)ceil_div(ceil_div(b, 16), kWaves);
-    const int64_t want = 2048 / (panels * ny);
+    const int64_t want = 1024 / (panels * ny);
     const int nrc = (int)std::max<int64_t>(1, std::min<int64_t>(max_chunks, want));
     const int64_t blocks = ceil_div(panels, 8) * 8 * ny * nrc;
     hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(kWaves * 64), lds, st, rows, (int)n, b,
